@@ -1,0 +1,169 @@
+/*
+ * hpscd.h - C ABI of libhpscd, an MI355X (gfx950) implementation of the HPSCD
+ * column-wise solver for X·a = y.
+ *
+ * The method (paper, Section 2, Algorithm 1; step derivation in Section 3):
+ * start from a = a0 (zero unless given) and e = y - X·a, then repeat sweeps
+ * over the columns j = 1..n in order:
+ *     da = <X_j, e> / <X_j, X_j>;   e <- e - X_j·da;   a_j <- a_j + da.
+ * Section 4 proves ||e|| never increases and tends to the least-squares
+ * minimum; Section 5 counts O(m) work per column step, O(mn) per sweep.
+ *
+ * Conventions shared by every entry point:
+ *  - X is column-major: column j starts at X + j*ldx.  Rows m..ldx-1 of a
+ *    column are never read as data (they may hold anything, NaN included).
+ *  - Array arguments named X*, y, a*, e*, *pool are DEVICE pointers owned by
+ *    the caller; arguments named hist, info, sys, sweeps_done, converged,
+ *    final_rel_resid, norm_out are HOST pointers owned by the caller.  The
+ *    library owns only the workspace held by its context.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is queued on
+ *    it in order; every solve call returns after the solve has finished,
+ *    because it fills host-side outputs.
+ *  - Arguments are validated before any device work.  On HPSCD_EINVAL no
+ *    output is written and hpscd_last_error() names the argument.
+ *  - A context is not thread-safe: use one context per host thread.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef HPSCD_H
+#define HPSCD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HPSCD_VERSION 1
+
+typedef struct hpscd_ctx hpscd_ctx;
+
+typedef enum {
+  HPSCD_OK = 0,
+  HPSCD_EINVAL = 1,     /* bad argument (nothing was run) */
+  HPSCD_ENOMEM = 2,     /* device workspace could not be allocated */
+  HPSCD_EDEVICE = 3,    /* HIP runtime error, or no usable device */
+  HPSCD_ENONFINITE = 4, /* X or y holds NaN/Inf (found before the first sweep), or the iteration overflowed */
+  HPSCD_EABORTED = 5,   /* hpscd_abort() was called during the solve */
+  HPSCD_ETIMEOUT = 6    /* a grid-wide reduction waited longer than the bound; results are invalid */
+} hpscd_status;
+
+/* Stopping rules.  Algorithm 1 runs a fixed number N of sweeps; Section 2
+ * allows breaking once the error is under a threshold (max_tol in the
+ * nomenclature) without defining the error.  hist[s] = ||e||_2 after sweep s. */
+typedef enum {
+  HPSCD_STOP_NONE = 0,       /* run exactly max_sweeps sweeps */
+  HPSCD_STOP_REL_CHANGE = 1, /* stop after sweep s >= 1 when hist[s-1] - hist[s] < tol*hist[s] */
+  HPSCD_STOP_REL_RESID = 2   /* stop when ||e|| < tol*||y||: tested before the first sweep, after
+                                every sweep, and every check_cols column steps if check_cols > 0 */
+} hpscd_stop;
+
+#define HPSCD_F_NO_FINAL_CHECK 1 /* skip the FP64 ||y - X·a|| pass (final_rel_resid = NaN) */
+#define HPSCD_F_FORCE_GRID 2     /* single system: use a persistent grid of workgroups */
+#define HPSCD_F_FORCE_WG 4       /* single system: use one workgroup */
+#define HPSCD_F_NO_COOP 8        /* launch the grid without hipLaunchCooperativeKernel */
+
+typedef struct {
+  int32_t max_sweeps;   /* N >= 0 */
+  int32_t stop;         /* hpscd_stop */
+  double tol;           /* finite, >= 0; ignored by HPSCD_STOP_NONE */
+  int64_t check_cols;   /* >= 0, see HPSCD_STOP_REL_RESID (rounded to the block size) */
+  int64_t refresh_cols; /* bf16 form: e = y - X32·a (FP64 sums) every refresh_cols column steps; 0 = never */
+  int32_t block;        /* columns per reduction round (1, 2, 4 or 8); 0 = library choice */
+  int32_t flags;        /* HPSCD_F_* */
+  int32_t team_threads; /* 0 = library choice */
+  int32_t reserved;
+} hpscd_opts;
+
+typedef struct {
+  int32_t sweeps_done;     /* complete sweeps */
+  int32_t converged;       /* 1 if a stop rule fired */
+  int64_t cols_done;       /* column steps performed */
+  int64_t zero_cols;       /* columns with <X_j, X_j> = 0, skipped (da = 0) */
+  double final_norm;       /* ||e||_2 of the running single-precision residual at exit */
+  double final_rel_resid;  /* ||y - X·a||_2 / ||y||_2 recomputed with FP64 sums (NaN if skipped) */
+  double y_norm;           /* ||y||_2 */
+  int32_t block_used;      /* B: columns per reduction round */
+  int32_t team_wgs;        /* workgroups in the team (1 = one workgroup) */
+  int32_t team_threads;    /* threads per workgroup */
+  int32_t refreshes;       /* residual refreshes queued (bf16 form) */
+  double sweep_ms;         /* device time of the sweep kernels (HIP events) */
+  double total_ms;         /* device time of the whole call (HIP events) */
+} hpscd_info;
+
+/* Fill *o with defaults: max_sweeps 100, HPSCD_STOP_NONE, tol 0, no checks,
+ * no refresh, block 0, flags 0. */
+void hpscd_default_opts(hpscd_opts* o);
+
+/* Create a context on HIP device `device` (owns the workspace).  Returns
+ * HPSCD_EDEVICE when no such device exists. */
+hpscd_status hpscd_create(int device, hpscd_ctx** out);
+void hpscd_destroy(hpscd_ctx* ctx);
+
+/* Check the arguments of hpscd_solve_f32 without touching a device (used by
+ * the solve itself first).  Returns HPSCD_OK or HPSCD_EINVAL. */
+hpscd_status hpscd_validate(int64_t m, int64_t n, const void* X, int64_t ldx, int elem_bytes, const void* y,
+                            const hpscd_opts* opts, const void* a_out);
+
+/* Solve X·a = y by Algorithm 1 in single precision (FP32 X, residual and
+ * products; FP64 sums of the per-workgroup partials, FP64 accumulation of a).
+ * X: m x n column-major FP32, 16-byte aligned, ldx >= m, ldx % 4 == 0.
+ * y: m floats.  a0: n floats or NULL (zero start).  a_out: n floats.
+ * hist: NULL or max_sweeps+1 doubles, hist[s] = ||e||_2 after sweep s for
+ * s <= sweeps_done.  info: NULL or filled on return. */
+hpscd_status hpscd_solve_f32(hpscd_ctx* ctx, int64_t m, int64_t n, const float* X, int64_t ldx, const float* y,
+                             const float* a0, const hpscd_opts* opts, float* a_out, double* hist,
+                             hpscd_info* info, void* stream);
+
+/* Reduced-precision storage form: the sweeps read X rounded to bfloat16
+ * (Xb, ldxb % 8 == 0) with FP32 products and residual; the starting residual,
+ * every residual refresh (opts->refresh_cols) and the final check use the FP32
+ * copy X32 with FP64 sums.  Other arguments as hpscd_solve_f32. */
+hpscd_status hpscd_solve_bf16(hpscd_ctx* ctx, int64_t m, int64_t n, const uint16_t* Xb, int64_t ldxb,
+                              const float* X32, int64_t ldx, const float* y, const float* a0,
+                              const hpscd_opts* opts, float* a_out, double* hist, hpscd_info* info, void* stream);
+
+/* dst = bfloat16(src), round to nearest, ties to even; rows x cols,
+ * column-major, ldd % 8 == 0, dst 16-byte aligned.  Rows rows..ldd-1 are
+ * written as zero. */
+hpscd_status hpscd_convert_bf16(hpscd_ctx* ctx, int64_t rows, int64_t cols, const float* src, int64_t lds,
+                                uint16_t* dst, int64_t ldd, void* stream);
+
+/* r = y - X·a with FP64 sums (the check of Section 4's e = y - X·a).
+ * e_out: NULL or m floats.  norm_out: NULL or host double, receives ||r||_2. */
+hpscd_status hpscd_residual_f64(hpscd_ctx* ctx, int64_t m, int64_t n, const float* X, int64_t ldx,
+                                const float* y, const float* a, float* e_out, double* norm_out, void* stream);
+
+/* Batched form: `count` independent systems in one persistent launch.
+ * sys[i] gives system i's sizes and element offsets into the pools; every
+ * system needs x_off % 4 == 0, ldx % 4 == 0, ldx >= m, 1 <= m <= 8192.
+ * a0pool: NULL or initial guesses at a_off.  apool: results at a_off.
+ * hist: NULL or count*(max_sweeps+1) doubles (row i for system i).
+ * sweeps_done, converged, final_rel_resid: NULL or count entries (host). */
+typedef struct {
+  int64_t m, n, x_off, ldx, y_off, a_off;
+} hpscd_sys;
+
+hpscd_status hpscd_solve_batched_f32(hpscd_ctx* ctx, int32_t count, const hpscd_sys* sys, const float* Xpool,
+                                     const float* ypool, const float* a0pool, const hpscd_opts* opts, float* apool,
+                                     double* hist, int32_t* sweeps_done, int32_t* converged,
+                                     double* final_rel_resid, hpscd_info* info, void* stream);
+
+/* Time the batched kernel's variants on this batch and remember the fastest
+ * for batches of the same shape (kept in the context). */
+hpscd_status hpscd_autotune_batched(hpscd_ctx* ctx, int32_t count, const hpscd_sys* sys, const float* Xpool,
+                                    const float* ypool, const hpscd_opts* opts, float* apool, void* stream);
+
+/* Ask a running solve on this context to stop at its next sweep boundary;
+ * that solve returns HPSCD_EABORTED.  Safe to call from another thread. */
+hpscd_status hpscd_abort(hpscd_ctx* ctx);
+
+/* Message of the last failure on this host thread ("" if none). */
+const char* hpscd_last_error(void);
+
+int hpscd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPSCD_H */

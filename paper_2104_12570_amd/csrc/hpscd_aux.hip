@@ -1,0 +1,522 @@
+// Auxiliary kernels of the HPSCD solver: column statistics, FP64 residuals,
+// bfloat16 conversion and small fills.
+//
+// Column statistics.  Algorithm 1 divides by <X_j, X_j> at every step; the
+// value is constant, so it is computed once per solve (FP64 sums) and stored
+// as its reciprocal (0 for a zero column, which the solver then skips).  For
+// blocks of B > 1 columns the sweep kernels also need the strictly-lower
+// in-block Gram entries <X_l, X_i>, i < l, computed in the same pass.
+//
+// Residual.  r = y - X·a with FP64 accumulation is used for the initial
+// residual of a warm start (Algorithm 1 forms e = y - X·a from the initial
+// guess), for the periodic refresh of the bfloat16-storage form, and for the
+// final FP64 check ||y - X·a||_2.
+#include "hpscd_device.hpp"
+#include "hpscd_internal.hpp"
+
+#include <float.h>
+
+namespace hpscd {
+
+template <class S>
+__device__ inline float chunk_at(const typename S::raw_t& r, int i) { return S::get(r, i); }
+
+// ------------------------------------------------------------- column stats
+// Grid (PR, NBG) of 256-thread workgroups.  Wave w of workgroup (rx, gy)
+// handles column blocks b = gy*4 + w (+ strides) over rows
+// [rx*rows_per, (rx+1)*rows_per) and writes its NP = B(B+1)/2 FP64 partial
+// sums (pair (l, i<=l) at l(l+1)/2 + i) to partial[(rx*nb + b)*NP].
+template <class S, int B>
+__global__ void __launch_bounds__(256) k_colgram(const void* X, int64_t ldx, int64_t m, int64_t n,
+                                                 int64_t rows_per, double* partial) {
+  using raw = typename S::raw_t;
+  constexpr int VEC = S::VEC, NP = B * (B + 1) / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t nb = (n + B - 1) / B;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t r1 = min(m, r0 + rows_per);
+  for (int64_t b = (int64_t)blockIdx.y * 4 + wave; b < nb; b += (int64_t)gridDim.y * 4) {
+    double acc[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+    for (int64_t row = r0 + (int64_t)lane * VEC; row < r1; row += 64 * VEC) {
+      const int lim = (int)min((int64_t)VEC, r1 - row);
+      raw x[B];
+#pragma unroll
+      for (int l = 0; l < B; ++l) {
+        const int64_t j = b * B + l;
+        x[l] = (j < n) ? load_chunk<S>(X, j * ldx + row) : S::zero();
+        if (lim < VEC) x[l] = mask_chunk<S>(x[l], lim);
+      }
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) {
+        double v[B];
+#pragma unroll
+        for (int l = 0; l < B; ++l) v[l] = (double)chunk_at<S>(x[l], i);
+#pragma unroll
+        for (int l = 0; l < B; ++l)
+#pragma unroll
+          for (int k = 0; k <= l; ++k) acc[l * (l + 1) / 2 + k] = fma(v[l], v[k], acc[l * (l + 1) / 2 + k]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const double s = wave_sum(acc[q]);
+      if (lane == q % 64) partial[((int64_t)blockIdx.x * nb + b) * NP + q] = s;
+    }
+  }
+}
+
+// Sum the PR partials (fixed order) into rdn[nb*B] and gram[nb*NG].
+template <int B>
+__global__ void k_colgram_reduce(const double* partial, int PR, int64_t n, double* rdn, double* gram,
+                                 int32_t* ctl, int64_t* zero_cols) {
+  constexpr int NP = B * (B + 1) / 2, NG = B * (B - 1) / 2;
+  const int64_t nb = (n + B - 1) / B;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nb * NP) return;
+  const int64_t b = idx / NP;
+  const int q = (int)(idx % NP);
+  double s = 0.0;
+  for (int r = 0; r < PR; ++r) s += partial[((int64_t)r * nb + b) * NP + q];
+  int l = 0;
+  while ((l + 1) * (l + 2) / 2 <= q) ++l;
+  const int i = q - l * (l + 1) / 2;
+  const int64_t j = b * B + l;
+  if (i == l) {
+    double r = 0.0;
+    if (j < n) {
+      if (!(s <= DBL_MAX)) store_flag(&ctl[CTL_NONFINITE], 1);
+      else if (s == 0.0) atomicAdd((unsigned long long*)zero_cols, 1ull);
+      else r = 1.0 / s;
+    }
+    rdn[b * B + l] = r;
+  } else {
+    gram[b * NG + l * (l - 1) / 2 + i] = (j < n) ? s : 0.0;
+  }
+}
+
+template <class S, int B>
+static hipError_t colgram_impl(const void* X, int64_t ldx, int64_t m, int64_t n, double* rdn, double* gram,
+                               double* partial, int64_t partial_cap, int32_t* ctl, int64_t* zero_cols,
+                               hipStream_t s) {
+  constexpr int NP = B * (B + 1) / 2;
+  const int64_t nb = (n + B - 1) / B;
+  // Enough waves to fill the chip (~8192), rows split only when the columns
+  // alone cannot provide them.
+  const int64_t waves_cols = nb;
+  int64_t PR = 1;
+  if (waves_cols < 8192) PR = (8192 + waves_cols - 1) / waves_cols;
+  const int64_t min_rows = 64 * S::VEC * 4;
+  PR = std::max<int64_t>(1, std::min<int64_t>(PR, (m + min_rows - 1) / min_rows));
+  while (PR > 1 && PR * nb * NP > partial_cap) --PR;
+  if (PR * nb * NP > partial_cap) return hipErrorInvalidValue;
+  int64_t rows_per = (m + PR - 1) / PR;
+  rows_per = (rows_per + S::VEC - 1) / S::VEC * S::VEC;
+  PR = (m + rows_per - 1) / rows_per;
+  const int64_t NBG = std::min<int64_t>((nb + 3) / 4, 65535);
+  hipLaunchKernelGGL((k_colgram<S, B>), dim3((unsigned)PR, (unsigned)NBG), dim3(256), 0, s, X, ldx, m, n,
+                     rows_per, partial);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const int64_t total = nb * NP;
+  hipLaunchKernelGGL((k_colgram_reduce<B>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, partial,
+                     (int)PR, n, rdn, gram, ctl, zero_cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_colgram(const void* X, bool bf16, int64_t ldx, int64_t m, int64_t n, int B, double* rdn,
+                          double* gram, double* partial, int64_t partial_cap, int32_t* ctl, int64_t* zero_cols,
+                          hipStream_t s) {
+#define HPSCD_CG(BB)                                                                               \
+  case BB:                                                                                         \
+    return bf16 ? colgram_impl<BF16, BB>(X, ldx, m, n, rdn, gram, partial, partial_cap, ctl, zero_cols, s) \
+                : colgram_impl<F32, BB>(X, ldx, m, n, rdn, gram, partial, partial_cap, ctl, zero_cols, s);
+  switch (B) {
+    HPSCD_CG(1) HPSCD_CG(2) HPSCD_CG(4) HPSCD_CG(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef HPSCD_CG
+}
+
+// Batched column statistics: one wave per (system, column block), all rows.
+template <int B>
+__global__ void __launch_bounds__(256) k_colgram_batched(const float* Xpool, const SysDesc* sys, int32_t count,
+                                                         int64_t nblk_total, const int64_t* blk_first,
+                                                         double* rdn, double* gram, int32_t* ctl) {
+  using S = F32;
+  using raw = S::raw_t;
+  constexpr int VEC = S::VEC, NP = B * (B + 1) / 2, NG = B * (B - 1) / 2;
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (g >= nblk_total) return;
+  int lo = 0, hi = count - 1;  // last system with blk_first <= g
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (blk_first[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  const SysDesc sd = sys[lo];
+  const int64_t b = g - blk_first[lo];
+  const float* X = Xpool + sd.x_off;
+  double acc[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+  for (int64_t row = (int64_t)lane * VEC; row < sd.m; row += 64 * VEC) {
+    const int lim = (int)min((int64_t)VEC, sd.m - row);
+    raw x[B];
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      const int64_t j = b * B + l;
+      x[l] = (j < sd.n) ? load_chunk<S>(X, j * sd.ldx + row) : S::zero();
+      if (lim < VEC) x[l] = mask_chunk<S>(x[l], lim);
+    }
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) {
+      double v[B];
+#pragma unroll
+      for (int l = 0; l < B; ++l) v[l] = (double)S::get(x[l], i);
+#pragma unroll
+      for (int l = 0; l < B; ++l)
+#pragma unroll
+        for (int k = 0; k <= l; ++k) acc[l * (l + 1) / 2 + k] = fma(v[l], v[k], acc[l * (l + 1) / 2 + k]);
+    }
+  }
+  double* r = rdn + sd.g_off + b * B;
+  double* gm = gram + (sd.g_off / B + b) * NG;
+#pragma unroll
+  for (int l = 0; l < B; ++l) {
+#pragma unroll
+    for (int k = 0; k <= l; ++k) {
+      const double s = wave_sum(acc[l * (l + 1) / 2 + k]);
+      if (lane == 0) {
+        const bool valid = (b * B + l) < sd.n;
+        if (k == l) {
+          if (valid && !(s <= DBL_MAX)) store_flag(&ctl[CTL_NONFINITE], 1);
+          r[l] = (valid && s > 0.0 && s <= DBL_MAX) ? 1.0 / s : 0.0;
+        } else {
+          gm[l * (l - 1) / 2 + k] = valid ? s : 0.0;
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_colgram_batched(const float* Xpool, const SysDesc* sys, int32_t count, int64_t nblk_total,
+                                  const int64_t* blk_first, int B, double* rdn, double* gram, int32_t* ctl,
+                                  hipStream_t s) {
+  const dim3 grid((unsigned)((nblk_total + 3) / 4));
+#define HPSCD_CGB(BB)                                                                                   \
+  case BB:                                                                                              \
+    hipLaunchKernelGGL((k_colgram_batched<BB>), grid, dim3(256), 0, s, Xpool, sys, count, nblk_total,    \
+                       blk_first, rdn, gram, ctl);                                                      \
+    return hipGetLastError();
+  switch (B) {
+    HPSCD_CGB(1) HPSCD_CGB(2) HPSCD_CGB(4) HPSCD_CGB(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef HPSCD_CGB
+}
+
+// ---------------------------------------------------------------- residual
+// Tall layout: one thread per chunk of 4 rows, looping over the columns.
+__global__ void __launch_bounds__(256) k_resid_rows(const float* X, int64_t ldx, int64_t m, int64_t ncols,
+                                                    const float* y, const double* a64, const float* a32,
+                                                    float* e_out, double* partial, const int32_t* skip_if) {
+  if (skip_if && *skip_if) return;
+  const int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int lim = row < m ? (int)min((int64_t)4, m - row) : 0;
+  if (lim > 0) {
+    for (int i = 0; i < lim; ++i) acc[i] = (double)y[row + i];
+    int64_t j = 0;
+    if (!a64 && !a32) ncols = 0;
+    for (; j + 4 <= ncols; j += 4) {
+      float4 x[4];
+      double aj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x[u] = load_chunk<F32>(X, (j + u) * ldx + row);
+        aj[u] = a64 ? a64[j + u] : (double)a32[j + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc[0] = fma(-(double)x[u].x, aj[u], acc[0]);
+        acc[1] = fma(-(double)x[u].y, aj[u], acc[1]);
+        acc[2] = fma(-(double)x[u].z, aj[u], acc[2]);
+        acc[3] = fma(-(double)x[u].w, aj[u], acc[3]);
+      }
+    }
+    for (; j < ncols; ++j) {
+      const float4 x = load_chunk<F32>(X, j * ldx + row);
+      const double aj = a64 ? a64[j] : (double)a32[j];
+      acc[0] = fma(-(double)x.x, aj, acc[0]);
+      acc[1] = fma(-(double)x.y, aj, acc[1]);
+      acc[2] = fma(-(double)x.z, aj, acc[2]);
+      acc[3] = fma(-(double)x.w, aj, acc[3]);
+    }
+  }
+  double sq = 0.0;
+  for (int i = 0; i < 4; ++i) {
+    if (i < lim) {
+      sq = fma(acc[i], acc[i], sq);
+      if (e_out) e_out[row + i] = (float)acc[i];
+    }
+  }
+  __shared__ double wsum[4];
+  sq = wave_sum(sq);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+}
+
+// Wide layout: workgroup g accumulates X[:, cols of g]·a for a tile of rows
+// into partial[g*m_tile + row] (FP64); k_resid_cols_reduce adds the partials.
+constexpr int RC_CHUNKS = 2;  // chunks per thread per row tile: 2048 rows per tile
+__global__ void __launch_bounds__(256) k_resid_cols(const float* X, int64_t ldx, int64_t m, int64_t row0,
+                                                    int64_t ncols, int64_t cols_per, const double* a64,
+                                                    const float* a32, double* partial, int64_t tile,
+                                                    const int32_t* skip_if) {
+  if (skip_if && *skip_if) return;
+  const int64_t c0 = (int64_t)blockIdx.x * cols_per, c1 = min(ncols, c0 + cols_per);
+  double acc[RC_CHUNKS][4];
+  int64_t rr[RC_CHUNKS];
+  int lim[RC_CHUNKS];
+#pragma unroll
+  for (int q = 0; q < RC_CHUNKS; ++q) {
+    rr[q] = row0 + ((int64_t)threadIdx.x + 256 * q) * 4;
+    lim[q] = rr[q] < m ? (int)min((int64_t)4, m - rr[q]) : 0;
+    for (int i = 0; i < 4; ++i) acc[q][i] = 0.0;
+  }
+  for (int64_t j = c0; j < c1; ++j) {
+    const double aj = a64 ? a64[j] : (a32 ? (double)a32[j] : 0.0);
+    if (aj == 0.0) continue;
+#pragma unroll
+    for (int q = 0; q < RC_CHUNKS; ++q) {
+      if (lim[q] > 0) {
+        float4 x = load_chunk<F32>(X, j * ldx + rr[q]);
+        if (lim[q] < 4) x = mask_chunk<F32>(x, lim[q]);
+        acc[q][0] = fma((double)x.x, aj, acc[q][0]);
+        acc[q][1] = fma((double)x.y, aj, acc[q][1]);
+        acc[q][2] = fma((double)x.z, aj, acc[q][2]);
+        acc[q][3] = fma((double)x.w, aj, acc[q][3]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RC_CHUNKS; ++q)
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = rr[q] - row0 + i;
+      if (r < tile) partial[(int64_t)blockIdx.x * tile + r] = acc[q][i];
+    }
+}
+
+__global__ void k_resid_cols_reduce(const double* partial, int G, int64_t tile, int64_t row0, int64_t m,
+                                    const float* y, float* e_out, double* sq_partial,
+                                    const int32_t* skip_if) {
+  if (skip_if && *skip_if) return;
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0;
+  if (r < tile && row0 + r < m) {
+    double s = 0.0;
+    for (int g = 0; g < G; ++g) s += partial[(int64_t)g * tile + r];
+    v = (double)y[row0 + r] - s;
+    if (e_out) e_out[row0 + r] = (float)v;
+  }
+  __shared__ double wsum[4];
+  double sq = wave_sum(v * v);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) sq_partial[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+}
+
+// Fixed-order sum of `count` doubles into *out (single workgroup).
+__global__ void __launch_bounds__(256) k_sum_f64(const double* v, int64_t count, double* out, int accumulate,
+                                                 const int32_t* skip_if) {
+  if (skip_if && *skip_if) return;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) s += v[i];
+  __shared__ double wsum[4];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+    *out = accumulate ? *out + t : t;
+  }
+}
+
+hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t ncols, const float* y,
+                           const double* a64, const float* a32, float* e_out, double* norm2, double* partial,
+                           int64_t partial_cap, const int32_t* skip_if, hipStream_t s) {
+  if (ncols == 0 || m >= 65536) {
+    const int64_t G = (m + 1023) / 1024;
+    if (G > partial_cap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_resid_rows, dim3((unsigned)G), dim3(256), 0, s, X, ldx, m, ncols, y, a64, a32, e_out,
+                       partial, skip_if);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    if (norm2) hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, s, partial, G, norm2, 0, skip_if);
+    return hipGetLastError();
+  }
+  // Column-split form for short, wide systems.
+  const int64_t tile = 256 * RC_CHUNKS * 4;
+  int64_t G = std::min<int64_t>(1024, std::max<int64_t>(1, ncols / 64));
+  const int64_t sqn = (tile + 255) / 256;
+  while (G > 1 && G * tile + sqn * ((m + tile - 1) / tile) > partial_cap) G /= 2;
+  const int64_t cols_per = (ncols + G - 1) / G;
+  G = (ncols + cols_per - 1) / cols_per;
+  const int64_t ntiles = (m + tile - 1) / tile;
+  if (G * tile + sqn * ntiles > partial_cap) return hipErrorInvalidValue;
+  double* sqp = partial + G * tile;
+  for (int64_t t = 0; t < ntiles; ++t) {
+    hipLaunchKernelGGL(k_resid_cols, dim3((unsigned)G), dim3(256), 0, s, X, ldx, m, t * tile, ncols, cols_per,
+                       a64, a32, partial, tile, skip_if);
+    hipLaunchKernelGGL(k_resid_cols_reduce, dim3((unsigned)sqn), dim3(256), 0, s, partial, (int)G, tile,
+                       t * tile, m, y, e_out, sqp + t * sqn, skip_if);
+  }
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  if (norm2) hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, s, sqp, sqn * ntiles, norm2, 0, skip_if);
+  return hipGetLastError();
+}
+
+// Batched residual: one workgroup per system.
+__global__ void __launch_bounds__(256) k_resid_batched(const float* Xpool, const float* ypool, const SysDesc* sys,
+                                                       const double* a64pool, const float* a32pool, float* e_out,
+                                                       double* norm2) {
+  const SysDesc sd = sys[blockIdx.x];
+  const float* X = Xpool + sd.x_off;
+  double sq = 0.0;
+  for (int64_t row = (int64_t)threadIdx.x * 4; row < sd.m; row += 1024) {
+    const int lim = (int)min((int64_t)4, sd.m - row);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < lim; ++i) acc[i] = (double)ypool[sd.y_off + row + i];
+    if (a64pool || a32pool) {
+      for (int64_t j = 0; j < sd.n; ++j) {
+        const double aj = a64pool ? a64pool[sd.a_off + j] : (double)a32pool[sd.a_off + j];
+        float4 x = load_chunk<F32>(X, j * sd.ldx + row);
+        if (lim < 4) x = mask_chunk<F32>(x, lim);
+        acc[0] = fma(-(double)x.x, aj, acc[0]);
+        acc[1] = fma(-(double)x.y, aj, acc[1]);
+        acc[2] = fma(-(double)x.z, aj, acc[2]);
+        acc[3] = fma(-(double)x.w, aj, acc[3]);
+      }
+    }
+    for (int i = 0; i < lim; ++i) {
+      sq = fma(acc[i], acc[i], sq);
+      if (e_out) e_out[sd.y_off + row + i] = (float)acc[i];
+    }
+  }
+  __shared__ double wsum[4];
+  sq = wave_sum(sq);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0 && norm2) norm2[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+}
+
+hipError_t launch_residual_batched(const float* Xpool, const float* ypool, const SysDesc* sys, int32_t count,
+                                   const double* a64pool, const float* a32pool, float* e_out, double* norm2,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(k_resid_batched, dim3((unsigned)count), dim3(256), 0, s, Xpool, ypool, sys, a64pool, a32pool,
+                     e_out, norm2);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------- conversion
+// FP32 -> bfloat16, round to nearest with ties to even on the 16 discarded
+// bits; NaN stays a quiet NaN.
+__device__ inline uint16_t to_bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu) != 0u) return (uint16_t)((u >> 16) | 0x0040u);
+  const uint32_t bias = 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)((u + bias) >> 16);
+}
+
+__global__ void __launch_bounds__(256) k_f32_to_bf16(const float* src, uint16_t* dst, int64_t rows, int64_t cols,
+                                                     int64_t lds, int64_t ldd) {
+  const int64_t per_col = (rows + 7) / 8;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= per_col * cols) return;
+  const int64_t j = idx / per_col, r = (idx % per_col) * 8;
+  uint16_t out[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) out[i] = (r + i < rows) ? to_bf16_rne(src[j * lds + r + i]) : (uint16_t)0;
+  uint4 w;
+  w.x = (uint32_t)out[0] | ((uint32_t)out[1] << 16);
+  w.y = (uint32_t)out[2] | ((uint32_t)out[3] << 16);
+  w.z = (uint32_t)out[4] | ((uint32_t)out[5] << 16);
+  w.w = (uint32_t)out[6] | ((uint32_t)out[7] << 16);
+  *reinterpret_cast<uint4*>(dst + j * ldd + r) = w;
+}
+
+hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, int64_t rows, int64_t cols, int64_t lds, int64_t ldd,
+                              hipStream_t s) {
+  const int64_t total = (rows + 7) / 8 * cols;
+  hipLaunchKernelGGL(k_f32_to_bf16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, rows, cols,
+                     lds, ldd);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------------- small
+__global__ void k_a_out(const double* a64, float* a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) a[i] = (float)a64[i];
+}
+__global__ void k_a_init(double* a64, const float* a0, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) a64[i] = a0 ? (double)a0[i] : 0.0;
+}
+__global__ void k_fill_u64(uint64_t* p, int64_t n, uint64_t v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_copy_f32(const float* s, float* d, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+
+__global__ void k_a_out_batched(const double* a64pool, float* apool, const SysDesc* sys) {
+  const SysDesc sd = sys[blockIdx.x];
+  for (int64_t j = threadIdx.x; j < sd.n; j += 256) apool[sd.a_off + j] = (float)a64pool[sd.a_off + j];
+}
+
+static inline dim3 g1(int64_t n) { return dim3((unsigned)std::max<int64_t>(1, (n + 255) / 256)); }
+
+hipError_t launch_a_out(const double* a64, float* a, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_a_out, g1(n), dim3(256), 0, s, a64, a, n);
+  return hipGetLastError();
+}
+hipError_t launch_a_out_batched(const double* a64pool, float* apool, const SysDesc* sys, int32_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_a_out_batched, dim3((unsigned)count), dim3(256), 0, s, a64pool, apool, sys);
+  return hipGetLastError();
+}
+hipError_t launch_a_init(double* a64, const float* a0, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_a_init, g1(n), dim3(256), 0, s, a64, a0, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, g1(n), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, g1(n), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f64, g1(n), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_f32, g1(n), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace hpscd

@@ -1,0 +1,724 @@
+// C ABI of libhpscd: argument validation, workspace, launch planning.
+#include "hpscd.h"
+#include "hpscd_device.hpp"
+#include "hpscd_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace hpscd;
+
+namespace {
+
+thread_local std::string g_err;
+
+hpscd_status fail(hpscd_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess) return fail(HPSCD_EDEVICE, "%s: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    size_t want = std::max(bytes, (size_t)256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) cap = want;
+    return e;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// Control block (one device allocation, read back with one copy).
+struct CtlBlock {
+  int32_t ctl[8];
+  int64_t ctl64[4];
+  double fstat[4];
+  double ynorm2;
+  double fnorm2;
+  double pad[2];
+};
+static_assert(sizeof(CtlBlock) == 128, "control block layout");
+
+constexpr uint64_t kTimeoutTicks = 1000000000ull;  // 10 s of the 100 MHz clock
+
+struct Tuned {
+  int B;
+};
+
+}  // namespace
+
+struct hpscd_ctx {
+  int device = 0;
+  int cus = 0;
+  DevBuf ctlb, e0, eo, a64, rdn, gram, partial, slots, hist;
+  DevBuf b_sys, b_items, b_blk, b_rdn, b_gram, b_a64, b_e0, b_hist, b_i32, b_f64;
+  void* host = nullptr;
+  size_t host_cap = 0;
+  hipStream_t side = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::map<std::string, Tuned> tuned;
+
+  hpscd_status host_ensure(size_t bytes) {
+    if (bytes <= host_cap) return HPSCD_OK;
+    if (host) (void)hipHostFree(host);
+    host = nullptr;
+    host_cap = 0;
+    if (hipHostMalloc(&host, bytes, hipHostMallocDefault) != hipSuccess)
+      return fail(HPSCD_ENOMEM, "pinned host buffer of %zu bytes", bytes);
+    host_cap = bytes;
+    return HPSCD_OK;
+  }
+};
+
+namespace {
+
+hpscd_status ensure(DevBuf& b, size_t bytes, const char* what) {
+  if (b.ensure(bytes) != hipSuccess) return fail(HPSCD_ENOMEM, "device workspace '%s' (%zu bytes)", what, bytes);
+  return HPSCD_OK;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+hpscd_status validate_opts(const hpscd_opts* o) {
+  if (!o) return fail(HPSCD_EINVAL, "opts is NULL");
+  if (o->max_sweeps < 0) return fail(HPSCD_EINVAL, "max_sweeps must be >= 0 (got %d)", o->max_sweeps);
+  if (o->stop < HPSCD_STOP_NONE || o->stop > HPSCD_STOP_REL_RESID)
+    return fail(HPSCD_EINVAL, "unknown stop rule %d", o->stop);
+  if (!std::isfinite(o->tol) || o->tol < 0.0) return fail(HPSCD_EINVAL, "tol must be finite and >= 0");
+  if (o->check_cols < 0) return fail(HPSCD_EINVAL, "check_cols must be >= 0");
+  if (o->refresh_cols < 0) return fail(HPSCD_EINVAL, "refresh_cols must be >= 0");
+  if (o->block != 0 && o->block != 1 && o->block != 2 && o->block != 4 && o->block != 8)
+    return fail(HPSCD_EINVAL, "block must be 0, 1, 2, 4 or 8 (got %d)", o->block);
+  if ((o->flags & HPSCD_F_FORCE_GRID) && (o->flags & HPSCD_F_FORCE_WG))
+    return fail(HPSCD_EINVAL, "FORCE_GRID and FORCE_WG are exclusive");
+  if ((int64_t)o->max_sweeps + 1 > (int64_t)1 << 30) return fail(HPSCD_EINVAL, "max_sweeps too large");
+  return HPSCD_OK;
+}
+
+// Largest block size <= want that divides every positive constraint.
+int pick_block(int want, std::initializer_list<int64_t> divides) {
+  for (int B = want; B >= 1; B /= 2) {
+    bool ok = true;
+    for (int64_t d : divides)
+      if (d > 0 && d % B != 0) ok = false;
+    if (ok) return B;
+  }
+  return 1;
+}
+
+struct Plan {
+  bool grid;
+  int T, R, B, P;
+};
+
+hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hpscd_opts* o, Plan* pl) {
+  const int VEC = bf16 ? 8 : 4;
+  bool grid;
+  if (o->flags & HPSCD_F_FORCE_GRID) grid = true;
+  else if (o->flags & HPSCD_F_FORCE_WG) grid = false;
+  else grid = m > 256 * (bf16 ? 2 : 4) * VEC;
+  std::vector<std::pair<int, int>> shapes;  // (T, R) candidates, smallest first
+  if (grid) {
+    if (bf16) shapes = {{1024, 1}, {512, 1}};
+    else if (m >= 256 * 1024 * 4) shapes = {{1024, 1}, {512, 2}};
+    else shapes = {{256, 1}, {1024, 1}};
+  } else {
+    if (bf16) shapes = {{256, 1}, {256, 2}};
+    else shapes = {{256, 2}, {256, 4}};
+  }
+  const int want = o->block > 0 ? o->block : (grid ? 8 : 4);
+  const int64_t need_n = o->refresh_cols > 0 ? n : 0;
+  int B = pick_block(want, {o->check_cols, o->refresh_cols, need_n});
+  if (o->block > 0 && B != o->block)
+    return fail(HPSCD_EINVAL, "block %d must divide check_cols, refresh_cols and (with refresh) n", o->block);
+  if (o->team_threads > 0) {
+    std::vector<std::pair<int, int>> keep;
+    for (int R : {1, 2, 4}) keep.push_back({o->team_threads, R});
+    shapes = keep;
+  }
+  for (auto [T, R] : shapes) {
+    const int64_t rows = (int64_t)T * R * VEC;
+    if (!grid && m > rows) continue;
+    int b = B;
+    while (b >= 1 && !sweep_variant_exists(T, R, b, bf16, grid)) b /= 2;
+    if (b < 1) continue;
+    if (o->block > 0 && b != o->block) continue;
+    const int64_t P = grid ? (m + rows - 1) / rows : 1;
+    if (grid) {
+      if (P > 512) continue;
+      const int per_cu = sweep_max_blocks_per_cu(T, R, b, bf16, true);
+      if (per_cu <= 0 || P > (int64_t)per_cu * c->cus) continue;
+    }
+    *pl = Plan{grid, T, R, b, (int)P};
+    return HPSCD_OK;
+  }
+  return fail(HPSCD_EINVAL, "no kernel variant fits m=%lld (%s team, block %d)", (long long)m,
+              grid ? "grid" : "workgroup", B);
+}
+
+hpscd_status validate_single(int64_t m, int64_t n, const void* X, int64_t ldx, int vec, const void* y,
+                             const hpscd_opts* o, const void* a_out) {
+  if (m < 1) return fail(HPSCD_EINVAL, "m must be >= 1 (got %lld)", (long long)m);
+  if (n < 1) return fail(HPSCD_EINVAL, "n must be >= 1 (got %lld)", (long long)n);
+  if (!X) return fail(HPSCD_EINVAL, "X is NULL");
+  if (!y) return fail(HPSCD_EINVAL, "y is NULL");
+  if (!a_out) return fail(HPSCD_EINVAL, "a_out is NULL");
+  if (ldx < m) return fail(HPSCD_EINVAL, "ldx (%lld) < m (%lld)", (long long)ldx, (long long)m);
+  if (ldx % vec != 0) return fail(HPSCD_EINVAL, "ldx (%lld) must be a multiple of %d", (long long)ldx, vec);
+  if (!aligned16(X)) return fail(HPSCD_EINVAL, "X must be 16-byte aligned");
+  if (n > (int64_t)1 << 40 || m > (int64_t)1 << 40) return fail(HPSCD_EINVAL, "system too large");
+  return validate_opts(o);
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.f;
+  return ms;
+}
+
+hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, int64_t ldxs, bool bf16,
+                          const float* X32, int64_t ldx32, const float* y, const float* a0, const hpscd_opts* o,
+                          float* a_out, double* hist, hpscd_info* info, hipStream_t st) {
+  Plan pl;
+  hpscd_status rc = plan_single(c, m, n, bf16, o, &pl);
+  if (rc != HPSCD_OK) return rc;
+  HIP_TRY(hipSetDevice(c->device));
+  const int B = pl.B;
+  const int64_t nb = (n + B - 1) / B;
+  const int NG = B * (B - 1) / 2;
+  const int64_t hist_len = (int64_t)o->max_sweeps + 1;
+  const int64_t partial_cap = std::max<int64_t>({(int64_t)1 << 21, nb * B * 80, (m + 1023) / 1024 + 8});
+
+  if ((rc = ensure(c->ctlb, sizeof(CtlBlock), "ctl")) ||
+      (rc = ensure(c->e0, (size_t)m * 4, "e0")) || (rc = ensure(c->eo, (size_t)m * 4, "e")) ||
+      (rc = ensure(c->a64, (size_t)n * 8, "a64")) || (rc = ensure(c->rdn, (size_t)nb * B * 8, "rdn")) ||
+      (rc = ensure(c->gram, (size_t)std::max<int64_t>(1, nb * NG) * 8, "gram")) ||
+      (rc = ensure(c->partial, (size_t)partial_cap * 8, "partial")) ||
+      (rc = ensure(c->slots, (size_t)2 * (B + 1) * std::max(1, pl.P) * 8, "slots")) ||
+      (rc = ensure(c->hist, (size_t)hist_len * 8, "hist")))
+    return rc;
+  if ((rc = c->host_ensure(sizeof(CtlBlock) + (size_t)hist_len * 8))) return rc;
+
+  CtlBlock* cb = c->ctlb.as<CtlBlock>();
+  int32_t* ctl = reinterpret_cast<int32_t*>(cb);
+  int64_t* ctl64 = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(cb) + offsetof(CtlBlock, ctl64));
+  double* fstat = reinterpret_cast<double*>(reinterpret_cast<char*>(cb) + offsetof(CtlBlock, fstat));
+  double* ynorm2 = reinterpret_cast<double*>(reinterpret_cast<char*>(cb) + offsetof(CtlBlock, ynorm2));
+  double* fnorm2 = reinterpret_cast<double*>(reinterpret_cast<char*>(cb) + offsetof(CtlBlock, fnorm2));
+  double* partial = c->partial.as<double>();
+
+  HIP_TRY(hipEventRecord(c->ev[0], st));
+  HIP_TRY(launch_fill_i32(ctl, sizeof(CtlBlock) / 4, 0, st));
+  HIP_TRY(launch_fill_f64(c->hist.as<double>(), hist_len, std::numeric_limits<double>::quiet_NaN(), st));
+  if (pl.grid) HIP_TRY(launch_fill_u64(c->slots.as<uint64_t>(), 2 * (int64_t)(B + 1) * pl.P, 0, st));
+  HIP_TRY(launch_a_init(c->a64.as<double>(), a0, n, st));
+  HIP_TRY(launch_residual(X32, ldx32, m, 0, y, nullptr, nullptr, nullptr, ynorm2, partial, partial_cap, nullptr, st));
+  const float* e0 = y;
+  if (a0) {
+    HIP_TRY(launch_residual(X32, ldx32, m, n, y, nullptr, a0, c->e0.as<float>(), nullptr, partial, partial_cap,
+                            nullptr, st));
+    e0 = c->e0.as<float>();
+  }
+  HIP_TRY(launch_colgram(Xs, bf16, ldxs, m, n, B, c->rdn.as<double>(), c->gram.as<double>(), partial, partial_cap,
+                         ctl, &ctl64[C64_ZERO_COLS], st));
+  HIP_TRY(hipEventRecord(c->ev[1], st));
+
+  SolveArgs A{};
+  A.X = Xs;
+  A.ldx = ldxs;
+  A.m = m;
+  A.n = n;
+  A.rdn = c->rdn.as<double>();
+  A.gram = c->gram.as<double>();
+  A.a64 = c->a64.as<double>();
+  A.e_out = c->eo.as<float>();
+  A.hist = c->hist.as<double>();
+  A.slots = c->slots.as<uint64_t>();
+  A.ctl = ctl;
+  A.fstat = fstat;
+  A.ctl64 = ctl64;
+  A.max_sweeps = o->max_sweeps;
+  A.stop = o->stop;
+  A.tol = o->tol;
+  A.ynorm2 = ynorm2;
+  A.check_cols = (o->stop == HPSCD_STOP_REL_RESID) ? o->check_cols : 0;
+  A.P = pl.P;
+  A.timeout_ticks = kTimeoutTicks;
+  const int64_t total = (int64_t)o->max_sweeps * nb + 1;
+  const int64_t seg = (o->refresh_cols > 0) ? std::max<int64_t>(1, o->refresh_cols / B) : total;
+  const bool coop = pl.grid && !(o->flags & HPSCD_F_NO_COOP);
+  int refreshes = 0;
+  for (int64_t kb = 0; kb < total; kb += seg) {
+    A.e0 = (kb == 0) ? e0 : c->eo.as<float>();
+    A.blk_begin = kb;
+    A.blk_end = std::min(total, kb + seg);
+    HIP_TRY(launch_sweep(pl.T, pl.R, B, bf16, pl.grid, A, st, coop));
+    if (o->refresh_cols > 0 && A.blk_end < total) {
+      const int64_t cols = (A.blk_end / nb) * n + (A.blk_end % nb) * B;
+      const int64_t touched = a0 ? n : std::min(n, cols);
+      HIP_TRY(launch_residual(X32, ldx32, m, touched, y, c->a64.as<double>(), nullptr, c->eo.as<float>(), nullptr,
+                              partial, partial_cap, &ctl[CTL_DONE], st));
+      ++refreshes;
+    }
+  }
+  HIP_TRY(hipEventRecord(c->ev[2], st));
+  HIP_TRY(launch_a_out(c->a64.as<double>(), a_out, n, st));
+  const bool check = !(o->flags & HPSCD_F_NO_FINAL_CHECK);
+  if (check)
+    HIP_TRY(launch_residual(X32, ldx32, m, n, y, c->a64.as<double>(), nullptr, nullptr, fnorm2, partial, partial_cap,
+                            nullptr, st));
+  HIP_TRY(hipEventRecord(c->ev[3], st));
+  CtlBlock* hc = reinterpret_cast<CtlBlock*>(c->host);
+  double* hh = reinterpret_cast<double*>(reinterpret_cast<char*>(c->host) + sizeof(CtlBlock));
+  HIP_TRY(hipMemcpyAsync(hc, cb, sizeof(CtlBlock), hipMemcpyDeviceToHost, st));
+  if (hist) HIP_TRY(hipMemcpyAsync(hh, c->hist.p, (size_t)hist_len * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+
+  if (hist) std::memcpy(hist, hh, (size_t)hist_len * 8);
+  if (info) {
+    std::memset(info, 0, sizeof *info);
+    info->sweeps_done = hc->ctl[CTL_SWEEPS];
+    info->converged = hc->ctl[CTL_CONVERGED];
+    info->cols_done = hc->ctl64[C64_COLS];
+    info->zero_cols = hc->ctl64[C64_ZERO_COLS];
+    info->final_norm = std::sqrt(hc->fstat[0]);
+    info->y_norm = std::sqrt(hc->ynorm2);
+    info->final_rel_resid = check ? (info->y_norm > 0 ? std::sqrt(hc->fnorm2) / info->y_norm : std::sqrt(hc->fnorm2))
+                                  : std::numeric_limits<double>::quiet_NaN();
+    info->block_used = B;
+    info->team_wgs = pl.P;
+    info->team_threads = pl.T;
+    info->refreshes = refreshes;
+    info->sweep_ms = elapsed(c->ev[1], c->ev[2]);
+    info->total_ms = elapsed(c->ev[0], c->ev[3]);
+  }
+  if (hc->ctl[CTL_NONFINITE]) return fail(HPSCD_ENONFINITE, "X or y holds a non-finite value");
+  if (hc->ctl[CTL_ERR] == ERR_TIMEOUT) return fail(HPSCD_ETIMEOUT, "grid reduction timed out");
+  if (hc->ctl[CTL_ERR] == ERR_ABORTED) return fail(HPSCD_EABORTED, "solve aborted");
+  if (hc->ctl[CTL_ERR] == ERR_NONFINITE) return fail(HPSCD_ENONFINITE, "the iteration produced a non-finite residual");
+  g_err.clear();
+  return HPSCD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hpscd_version(void) { return HPSCD_VERSION; }
+
+const char* hpscd_last_error(void) { return g_err.c_str(); }
+
+void hpscd_default_opts(hpscd_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->max_sweeps = 100;
+  o->stop = HPSCD_STOP_NONE;
+}
+
+hpscd_status hpscd_create(int device, hpscd_ctx** out) {
+  try {
+    if (!out) return fail(HPSCD_EINVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return fail(HPSCD_EDEVICE, "no HIP device");
+    if (device < 0 || device >= count) return fail(HPSCD_EDEVICE, "device %d out of range (%d devices)", device, count);
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    hpscd_ctx* c = new hpscd_ctx();
+    c->device = device;
+    c->cus = prop.multiProcessorCount;
+    for (auto& e : c->ev)
+      if (hipEventCreate(&e) != hipSuccess) { delete c; return fail(HPSCD_EDEVICE, "hipEventCreate"); }
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(HPSCD_EDEVICE, "hipStreamCreateWithFlags");
+    }
+    *out = c;
+    g_err.clear();
+    return HPSCD_OK;
+  } catch (...) {
+    return fail(HPSCD_ENOMEM, "allocation failure");
+  }
+}
+
+void hpscd_destroy(hpscd_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (DevBuf* b : {&c->ctlb, &c->e0, &c->eo, &c->a64, &c->rdn, &c->gram, &c->partial, &c->slots, &c->hist,
+                    &c->b_sys, &c->b_items, &c->b_blk, &c->b_rdn, &c->b_gram, &c->b_a64, &c->b_e0, &c->b_hist,
+                    &c->b_i32, &c->b_f64})
+    b->release();
+  if (c->host) (void)hipHostFree(c->host);
+  for (auto& e : c->ev) if (e) (void)hipEventDestroy(e);
+  if (c->side) (void)hipStreamDestroy(c->side);
+  delete c;
+}
+
+hpscd_status hpscd_validate(int64_t m, int64_t n, const void* X, int64_t ldx, int elem_bytes, const void* y,
+                            const hpscd_opts* opts, const void* a_out) {
+  if (elem_bytes != 4 && elem_bytes != 2) return fail(HPSCD_EINVAL, "elem_bytes must be 4 or 2");
+  return validate_single(m, n, X, ldx, elem_bytes == 4 ? 4 : 8, y, opts, a_out);
+}
+
+hpscd_status hpscd_solve_f32(hpscd_ctx* ctx, int64_t m, int64_t n, const float* X, int64_t ldx, const float* y,
+                             const float* a0, const hpscd_opts* opts, float* a_out, double* hist, hpscd_info* info,
+                             void* stream) {
+  try {
+    hpscd_status rc = validate_single(m, n, X, ldx, 4, y, opts, a_out);
+    if (rc != HPSCD_OK) return rc;
+    if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
+    return solve_single(ctx, m, n, X, ldx, false, X, ldx, y, a0, opts, a_out, hist, info, (hipStream_t)stream);
+  } catch (...) {
+    return fail(HPSCD_ENOMEM, "host allocation failure");
+  }
+}
+
+hpscd_status hpscd_solve_bf16(hpscd_ctx* ctx, int64_t m, int64_t n, const uint16_t* Xb, int64_t ldxb, const float* X32,
+                              int64_t ldx, const float* y, const float* a0, const hpscd_opts* opts, float* a_out,
+                              double* hist, hpscd_info* info, void* stream) {
+  try {
+    hpscd_status rc = validate_single(m, n, Xb, ldxb, 8, y, opts, a_out);
+    if (rc != HPSCD_OK) return rc;
+    if (!X32) return fail(HPSCD_EINVAL, "X32 is NULL");
+    if (ldx < m || ldx % 4 != 0 || !aligned16(X32))
+      return fail(HPSCD_EINVAL, "X32 needs ldx >= m, ldx %% 4 == 0 and 16-byte alignment");
+    if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
+    return solve_single(ctx, m, n, Xb, ldxb, true, X32, ldx, y, a0, opts, a_out, hist, info, (hipStream_t)stream);
+  } catch (...) {
+    return fail(HPSCD_ENOMEM, "host allocation failure");
+  }
+}
+
+hpscd_status hpscd_convert_bf16(hpscd_ctx* ctx, int64_t rows, int64_t cols, const float* src, int64_t lds,
+                                uint16_t* dst, int64_t ldd, void* stream) {
+  if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
+  if (rows < 1 || cols < 1) return fail(HPSCD_EINVAL, "rows and cols must be >= 1");
+  if (!src || !dst) return fail(HPSCD_EINVAL, "NULL array");
+  if (lds < rows || ldd < rows || ldd % 8 != 0 || !aligned16(dst))
+    return fail(HPSCD_EINVAL, "need lds >= rows, ldd >= rows, ldd %% 8 == 0, dst 16-byte aligned");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(launch_f32_to_bf16(src, dst, rows, cols, lds, ldd, (hipStream_t)stream));
+  return HPSCD_OK;
+}
+
+hpscd_status hpscd_residual_f64(hpscd_ctx* ctx, int64_t m, int64_t n, const float* X, int64_t ldx, const float* y,
+                                const float* a, float* e_out, double* norm_out, void* stream) {
+  if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
+  if (m < 1 || n < 1 || !X || !y || !a) return fail(HPSCD_EINVAL, "bad residual arguments");
+  if (ldx < m || ldx % 4 != 0 || !aligned16(X)) return fail(HPSCD_EINVAL, "X layout");
+  HIP_TRY(hipSetDevice(ctx->device));
+  const int64_t cap = std::max<int64_t>((int64_t)1 << 21, (m + 1023) / 1024 + 8);
+  hpscd_status rc;
+  if ((rc = ensure(ctx->partial, (size_t)cap * 8, "partial")) || (rc = ensure(ctx->ctlb, sizeof(CtlBlock), "ctl")))
+    return rc;
+  if ((rc = ctx->host_ensure(64))) return rc;
+  double* d = reinterpret_cast<double*>(reinterpret_cast<char*>(ctx->ctlb.p) + offsetof(CtlBlock, fnorm2));
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(launch_residual(X, ldx, m, n, y, nullptr, a, e_out, d, ctx->partial.as<double>(), cap, nullptr, st));
+  if (norm_out) {
+    HIP_TRY(hipMemcpyAsync(ctx->host, d, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *norm_out = std::sqrt(*reinterpret_cast<double*>(ctx->host));
+  }
+  return HPSCD_OK;
+}
+
+hpscd_status hpscd_abort(hpscd_ctx* ctx) {
+  if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
+  if (!ctx->ctlb.p) return HPSCD_OK;
+  static const int32_t one = 1;
+  HIP_TRY(hipMemcpyAsync(ctx->ctlb.p, &one, 4, hipMemcpyHostToDevice, ctx->side));
+  HIP_TRY(hipStreamSynchronize(ctx->side));
+  return HPSCD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batched
+namespace {
+
+struct BatchPlan {
+  std::vector<SysDesc> sd;
+  std::vector<WorkItem> items;
+  std::vector<int64_t> blk_first;
+  int64_t nblk = 0, a_size = 0, y_size = 0, rdn_size = 0, gram_size = 0;
+};
+
+hpscd_status validate_batch(int32_t count, const hpscd_sys* sys, const float* Xpool, const float* ypool,
+                            const hpscd_opts* o, const float* apool) {
+  if (count < 1) return fail(HPSCD_EINVAL, "count must be >= 1");
+  if (!sys) return fail(HPSCD_EINVAL, "sys is NULL");
+  if (!Xpool || !ypool || !apool) return fail(HPSCD_EINVAL, "NULL pool");
+  if (!aligned16(Xpool)) return fail(HPSCD_EINVAL, "Xpool must be 16-byte aligned");
+  const int64_t max_m = batched_rows_per_wg();
+  for (int32_t i = 0; i < count; ++i) {
+    const hpscd_sys& s = sys[i];
+    if (s.m < 1 || s.n < 1) return fail(HPSCD_EINVAL, "system %d: m and n must be >= 1", i);
+    if (s.m > max_m) return fail(HPSCD_EINVAL, "system %d: m=%lld exceeds %lld", i, (long long)s.m, (long long)max_m);
+    if (s.ldx < s.m || s.ldx % 4 != 0) return fail(HPSCD_EINVAL, "system %d: need ldx >= m and ldx %% 4 == 0", i);
+    if (s.x_off < 0 || s.x_off % 4 != 0) return fail(HPSCD_EINVAL, "system %d: x_off must be >= 0 and %% 4 == 0", i);
+    if (s.y_off < 0 || s.a_off < 0) return fail(HPSCD_EINVAL, "system %d: negative offset", i);
+  }
+  return validate_opts(o);
+}
+
+// Work items in longest-processing-time order: systems that fit one wave are
+// grouped four to an item by decreasing size; larger systems get a whole
+// workgroup.  The queue hands items out in this order.
+void plan_batch(int32_t count, const hpscd_sys* sys, int B, int hist_len, BatchPlan* bp) {
+  bp->sd.resize(count);
+  bp->blk_first.resize(count);
+  int64_t g = 0, blk = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const hpscd_sys& s = sys[i];
+    const int64_t nb = (s.n + B - 1) / B;
+    bp->sd[i] = SysDesc{s.m, s.n, s.x_off, s.ldx, s.y_off, s.a_off, g, (int64_t)i * hist_len};
+    bp->blk_first[i] = blk;
+    g += nb * B;
+    blk += nb;
+    bp->a_size = std::max(bp->a_size, s.a_off + s.n);
+    bp->y_size = std::max(bp->y_size, s.y_off + s.m);
+  }
+  bp->nblk = blk;
+  bp->rdn_size = g;
+  bp->gram_size = g / B * (B * (B - 1) / 2);
+  std::vector<int32_t> small, big;
+  const int64_t wave_rows = batched_rows_per_wave();
+  for (int32_t i = 0; i < count; ++i) (sys[i].m <= wave_rows ? small : big).push_back(i);
+  auto work = [&](int32_t i) { return (double)sys[i].m * (double)sys[i].n; };
+  auto by_work = [&](int32_t a, int32_t b) { return work(a) > work(b); };
+  std::sort(small.begin(), small.end(), by_work);
+  std::sort(big.begin(), big.end(), by_work);
+  std::vector<std::pair<double, WorkItem>> items;
+  for (int32_t i : big) items.push_back({work(i), WorkItem{0, 1, {i, 0, 0, 0}}});
+  const int per = batched_threads() / WAVE;
+  for (size_t k = 0; k < small.size(); k += per) {
+    WorkItem w{1, 0, {0, 0, 0, 0}};
+    for (int q = 0; q < per && k + q < small.size(); ++q) w.sys[w.count++] = small[k + q];
+    items.push_back({work(small[k]), w});
+  }
+  std::stable_sort(items.begin(), items.end(), [](auto& a, auto& b) { return a.first > b.first; });
+  bp->items.clear();
+  for (auto& it : items) bp->items.push_back(it.second);
+}
+
+std::string batch_key(int32_t count, const hpscd_sys* sys) {
+  // shape signature: count and a coarse histogram of sizes
+  int64_t sm = 0, sn = 0, smn = 0;
+  for (int32_t i = 0; i < count; ++i) { sm += sys[i].m; sn += sys[i].n; smn += sys[i].m * sys[i].n; }
+  char buf[128];
+  snprintf(buf, sizeof buf, "%d:%lld:%lld:%lld", count, (long long)sm, (long long)sn, (long long)smn);
+  return buf;
+}
+
+hpscd_status solve_batched(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, const float* Xpool, const float* ypool,
+                           const float* a0pool, const hpscd_opts* o, int B, float* apool, double* hist,
+                           int32_t* sweeps_done, int32_t* converged, double* final_rel, hpscd_info* info,
+                           hipStream_t st) {
+  HIP_TRY(hipSetDevice(c->device));
+  const int hist_len = o->max_sweeps + 1;
+  BatchPlan bp;
+  plan_batch(count, sys, B, hist_len, &bp);
+  const int nitems = (int)bp.items.size();
+  hpscd_status rc;
+  const size_t sys_bytes = bp.sd.size() * sizeof(SysDesc);
+  const size_t item_bytes = bp.items.size() * sizeof(WorkItem);
+  const size_t blk_bytes = bp.blk_first.size() * sizeof(int64_t);
+  // i32 region: queue[4], sweeps[count], converged[count], ctl[8]
+  const size_t i32_n = 16 + 2 * (size_t)count;
+  // f64 region: ynorm2[count], fnorm2[count]
+  const size_t f64_n = 2 * (size_t)count;
+  if ((rc = ensure(c->b_sys, sys_bytes, "sys")) || (rc = ensure(c->b_items, item_bytes, "items")) ||
+      (rc = ensure(c->b_blk, blk_bytes, "blk")) || (rc = ensure(c->b_rdn, (size_t)bp.rdn_size * 8, "rdn")) ||
+      (rc = ensure(c->b_gram, (size_t)std::max<int64_t>(1, bp.gram_size) * 8, "gram")) ||
+      (rc = ensure(c->b_a64, (size_t)bp.a_size * 8, "a64")) ||
+      (rc = ensure(c->b_e0, a0pool ? (size_t)bp.y_size * 4 : 4, "e0")) ||
+      (rc = ensure(c->b_hist, (size_t)count * hist_len * 8, "hist")) || (rc = ensure(c->b_i32, i32_n * 4, "i32")) ||
+      (rc = ensure(c->b_f64, f64_n * 8, "f64")))
+    return rc;
+  const size_t up = sys_bytes + item_bytes + blk_bytes;
+  const size_t down = i32_n * 4 + f64_n * 8 + (hist ? (size_t)count * hist_len * 8 : 0);
+  if ((rc = c->host_ensure(std::max(up, down) + 64))) return rc;
+  // The staging buffer is reused for the download only after the stream has
+  // drained the uploads (the synchronisation below).
+  char* h = reinterpret_cast<char*>(c->host);
+  std::memcpy(h, bp.sd.data(), sys_bytes);
+  std::memcpy(h + sys_bytes, bp.items.data(), item_bytes);
+  std::memcpy(h + sys_bytes + item_bytes, bp.blk_first.data(), blk_bytes);
+  HIP_TRY(hipEventRecord(c->ev[0], st));
+  HIP_TRY(hipMemcpyAsync(c->b_sys.p, h, sys_bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(c->b_items.p, h + sys_bytes, item_bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(c->b_blk.p, h + sys_bytes + item_bytes, blk_bytes, hipMemcpyHostToDevice, st));
+  int32_t* i32 = c->b_i32.as<int32_t>();
+  int32_t* queue = i32;
+  int32_t* ctl = i32 + 4;
+  int32_t* d_sweeps = i32 + 16;
+  int32_t* d_conv = d_sweeps + count;
+  double* ynorm2 = c->b_f64.as<double>();
+  double* fnorm2 = ynorm2 + count;
+  const SysDesc* dsys = c->b_sys.as<SysDesc>();
+  HIP_TRY(launch_fill_i32(i32, (int64_t)i32_n, 0, st));
+  HIP_TRY(launch_fill_f64(c->b_hist.as<double>(), (int64_t)count * hist_len, std::numeric_limits<double>::quiet_NaN(), st));
+  HIP_TRY(launch_a_init(c->b_a64.as<double>(), a0pool, bp.a_size, st));
+  HIP_TRY(launch_residual_batched(Xpool, ypool, dsys, count, nullptr, nullptr, nullptr, ynorm2, st));
+  const float* e0 = ypool;
+  if (a0pool) {
+    HIP_TRY(launch_residual_batched(Xpool, ypool, dsys, count, nullptr, a0pool, c->b_e0.as<float>(), nullptr, st));
+    e0 = c->b_e0.as<float>();
+  }
+  HIP_TRY(launch_colgram_batched(Xpool, dsys, count, bp.nblk, c->b_blk.as<int64_t>(), B, c->b_rdn.as<double>(),
+                                 c->b_gram.as<double>(), ctl + CTL_NONFINITE, st));
+  HIP_TRY(hipEventRecord(c->ev[1], st));
+  BatchArgs A{};
+  A.Xpool = Xpool;
+  A.ypool = ypool;
+  A.sys = dsys;
+  A.items = c->b_items.as<WorkItem>();
+  A.nitems = nitems;
+  A.queue = queue;
+  A.rdn = c->b_rdn.as<double>();
+  A.gram = c->b_gram.as<double>();
+  A.e0pool = e0;
+  A.a64pool = c->b_a64.as<double>();
+  A.hist = c->b_hist.as<double>();
+  A.sweeps = d_sweeps;
+  A.converged = d_conv;
+  A.max_sweeps = o->max_sweeps;
+  A.stop = o->stop;
+  A.tol = o->tol;
+  A.ynorm2 = ynorm2;
+  const int per_cu = batched_max_blocks_per_cu(B);
+  if (per_cu <= 0) return fail(HPSCD_EDEVICE, "batched kernel cannot be resident");
+  const int grid = std::max(1, std::min(nitems, per_cu * c->cus));
+  HIP_TRY(launch_batched(B, A, grid, st));
+  HIP_TRY(hipEventRecord(c->ev[2], st));
+  HIP_TRY(launch_a_out_batched(c->b_a64.as<double>(), apool, dsys, count, st));
+  const bool check = !(o->flags & HPSCD_F_NO_FINAL_CHECK);
+  if (check) HIP_TRY(launch_residual_batched(Xpool, ypool, dsys, count, c->b_a64.as<double>(), nullptr, nullptr, fnorm2, st));
+  HIP_TRY(hipEventRecord(c->ev[3], st));
+  HIP_TRY(hipStreamSynchronize(st));  // uploads done; staging may be reused
+  HIP_TRY(hipMemcpyAsync(h, i32, i32_n * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(h + i32_n * 4, ynorm2, f64_n * 8, hipMemcpyDeviceToHost, st));
+  if (hist)
+    HIP_TRY(hipMemcpyAsync(h + i32_n * 4 + f64_n * 8, c->b_hist.p, (size_t)count * hist_len * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const int32_t* hi = reinterpret_cast<const int32_t*>(h);
+  const double* hy = reinterpret_cast<const double*>(h + i32_n * 4);
+  if (sweeps_done) std::memcpy(sweeps_done, hi + 16, (size_t)count * 4);
+  if (converged) std::memcpy(converged, hi + 16 + count, (size_t)count * 4);
+  if (final_rel)
+    for (int32_t i = 0; i < count; ++i) {
+      const double yn = std::sqrt(hy[i]);
+      final_rel[i] = check ? (yn > 0 ? std::sqrt(hy[count + i]) / yn : std::sqrt(hy[count + i]))
+                           : std::numeric_limits<double>::quiet_NaN();
+    }
+  if (hist) std::memcpy(hist, h + i32_n * 4 + f64_n * 8, (size_t)count * hist_len * 8);
+  if (info) {
+    std::memset(info, 0, sizeof *info);
+    int64_t swsum = 0, cvsum = 0;
+    for (int32_t i = 0; i < count; ++i) { swsum += hi[16 + i]; cvsum += hi[16 + count + i]; }
+    info->sweeps_done = (int32_t)std::min<int64_t>(swsum, INT32_MAX);
+    info->converged = (int32_t)cvsum;
+    int64_t cols = 0;
+    for (int32_t i = 0; i < count; ++i) cols += (int64_t)hi[16 + i] * sys[i].n;
+    info->cols_done = cols;
+    info->block_used = B;
+    info->team_wgs = grid;
+    info->team_threads = batched_threads();
+    info->sweep_ms = elapsed(c->ev[1], c->ev[2]);
+    info->total_ms = elapsed(c->ev[0], c->ev[3]);
+    info->final_rel_resid = std::numeric_limits<double>::quiet_NaN();
+  }
+  if (hi[4 + CTL_NONFINITE]) return fail(HPSCD_ENONFINITE, "a system holds a non-finite value");
+  g_err.clear();
+  return HPSCD_OK;
+}
+
+int batched_block(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, const hpscd_opts* o) {
+  if (o->block > 0) return o->block;
+  auto it = c->tuned.find(batch_key(count, sys));
+  return it != c->tuned.end() ? it->second.B : 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+hpscd_status hpscd_solve_batched_f32(hpscd_ctx* ctx, int32_t count, const hpscd_sys* sys, const float* Xpool,
+                                     const float* ypool, const float* a0pool, const hpscd_opts* opts, float* apool,
+                                     double* hist, int32_t* sweeps_done, int32_t* converged,
+                                     double* final_rel_resid, hpscd_info* info, void* stream) {
+  try {
+    hpscd_status rc = validate_batch(count, sys, Xpool, ypool, opts, apool);
+    if (rc != HPSCD_OK) return rc;
+    if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
+    const int B = batched_block(ctx, count, sys, opts);
+    if (!batched_variant_exists(B)) return fail(HPSCD_EINVAL, "batched block %d is not built", B);
+    return solve_batched(ctx, count, sys, Xpool, ypool, a0pool, opts, B, apool, hist, sweeps_done, converged,
+                         final_rel_resid, info, (hipStream_t)stream);
+  } catch (...) {
+    return fail(HPSCD_ENOMEM, "host allocation failure");
+  }
+}
+
+hpscd_status hpscd_autotune_batched(hpscd_ctx* ctx, int32_t count, const hpscd_sys* sys, const float* Xpool,
+                                    const float* ypool, const hpscd_opts* opts, float* apool, void* stream) {
+  try {
+    hpscd_status rc = validate_batch(count, sys, Xpool, ypool, opts, apool);
+    if (rc != HPSCD_OK) return rc;
+    if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
+    double best = 1e300;
+    int bestB = 1;
+    for (int B : {1, 2, 4}) {
+      if (!batched_variant_exists(B)) continue;
+      double t = 1e300;
+      for (int rep = 0; rep < 2; ++rep) {
+        hpscd_info inf;
+        rc = solve_batched(ctx, count, sys, Xpool, ypool, nullptr, opts, B, apool, nullptr, nullptr, nullptr,
+                           nullptr, &inf, (hipStream_t)stream);
+        if (rc != HPSCD_OK) return rc;
+        t = std::min(t, inf.total_ms);
+      }
+      if (t < best) { best = t; bestB = B; }
+    }
+    ctx->tuned[batch_key(count, sys)] = Tuned{bestB};
+    g_err.clear();
+    return HPSCD_OK;
+  } catch (...) {
+    return fail(HPSCD_ENOMEM, "host allocation failure");
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Host-side declarations shared by the HPSCD translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hpscd {
+
+// Arguments of one sweep-kernel launch (single system, grid or one workgroup).
+struct SolveArgs {
+  const void* X;          // column-major m x n, 16-byte aligned columns
+  int64_t ldx, m, n;
+  const float* e0;        // residual at entry (length m)
+  const double* rdn;      // [nb*B] 1/<X_j,X_j> (0 for zero and padding columns)
+  const double* gram;     // [nb][B*(B-1)/2] strictly-lower in-block Gram, (l,i) row-major
+  double* a64;            // [n] coefficients, accumulated in FP64
+  float* e_out;           // [m] residual at exit
+  double* hist;           // [max_sweeps+1] ||e||_2 after each complete sweep
+  uint64_t* slots;        // grid exchange words [2][B+1][P]
+  int32_t* ctl;           // control words (Ctl)
+  double* fstat;          // [0] ||e||^2 at exit, [1] last recorded sweep norm
+  int64_t* ctl64;         // [C64_COLS] column steps done
+  int32_t max_sweeps;
+  int32_t stop;
+  double tol;
+  const double* ynorm2;   // device: ||y||^2
+  int64_t check_cols;
+  int64_t blk_begin;      // first global block index of this launch
+  int64_t blk_end;        // one past the last global block index of this launch
+  int32_t P;              // workgroups in the grid (1 for a workgroup team)
+  uint64_t timeout_ticks; // bound on any spin-wait (100 MHz ticks)
+};
+
+// One system of a batch as the batched kernels see it (element offsets).
+struct SysDesc {
+  int64_t m, n, x_off, ldx, y_off, a_off;
+  int64_t g_off;          // offset of this system's rdn/gram region
+  int64_t h_off;          // offset of this system's hist region
+};
+
+// One unit of batched work: a system solved by the whole workgroup, or up to
+// four systems solved by one wave each.
+struct WorkItem {
+  int32_t mode;           // 0 = workgroup team, 1 = wave teams
+  int32_t count;          // systems in the item
+  int32_t sys[4];
+};
+
+struct BatchArgs {
+  const float* Xpool;
+  const float* ypool;
+  const SysDesc* sys;
+  const WorkItem* items;
+  int32_t nitems;
+  int32_t* queue;          // atomic work counter (zeroed before launch)
+  const double* rdn;       // per-system regions at sys.g_off
+  const double* gram;      // per-system regions at sys.g_off*(B-1)/2
+  const float* e0pool;     // initial residuals (ypool when a0 is absent)
+  double* a64pool;         // [a_size]
+  double* hist;            // per-system hist regions at sys.h_off
+  int32_t* sweeps;         // [count]
+  int32_t* converged;      // [count]
+  int32_t max_sweeps;
+  int32_t stop;
+  double tol;
+  const double* ynorm2;    // [count] ||y_i||^2
+};
+
+// Kernel launchers (return hipError_t of the launch).
+hipError_t launch_sweep(int variant_T, int variant_R, int B, bool bf16, bool grid,
+                        const SolveArgs& a, hipStream_t s, bool cooperative);
+int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid);
+bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid);
+
+hipError_t launch_batched(int B, const BatchArgs& a, int grid, hipStream_t s);
+int batched_threads();
+int batched_rows_per_wave();
+int batched_rows_per_wg();
+int batched_max_blocks_per_cu(int B);
+bool batched_variant_exists(int B);
+
+// Column statistics: rdn = 1/<X_j,X_j> and the in-block Gram, FP64 sums.
+hipError_t launch_colgram(const void* X, bool bf16, int64_t ldx, int64_t m, int64_t n, int B,
+                          double* rdn, double* gram, double* partial, int64_t partial_cap,
+                          int32_t* ctl, int64_t* zero_cols, hipStream_t s);
+hipError_t launch_colgram_batched(const float* Xpool, const SysDesc* sys, int32_t count, int64_t nblk_total,
+                                  const int64_t* blk_first, int B, double* rdn, double* gram,
+                                  int32_t* ctl, hipStream_t s);
+// r = y - X[:, :ncols]·a (FP64 accumulation); optional FP32 copy to e_out and
+// ||r||^2 into *norm2 (device double).
+hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t ncols, const float* y,
+                           const double* a64, const float* a32, float* e_out, double* norm2,
+                           double* partial, int64_t partial_cap, const int32_t* skip_if, hipStream_t s);
+hipError_t launch_residual_batched(const float* Xpool, const float* ypool, const SysDesc* sys, int32_t count,
+                                   const double* a64pool, const float* a32pool, float* e_out,
+                                   double* norm2, hipStream_t s);
+hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, int64_t rows, int64_t cols,
+                              int64_t lds, int64_t ldd, hipStream_t s);
+hipError_t launch_a_out(const double* a64, float* a, int64_t n, hipStream_t s);
+hipError_t launch_a_out_batched(const double* a64pool, float* apool, const SysDesc* sys, int32_t count, hipStream_t s);
+hipError_t launch_a_init(double* a64, const float* a0, int64_t n, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s);
+
+}  // namespace hpscd

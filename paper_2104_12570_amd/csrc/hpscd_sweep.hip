@@ -1,0 +1,601 @@
+// Sweep kernels of the HPSCD solver (paper, Section 2, Algorithm 1).
+//
+// One step of Algorithm 1 for column j is
+//     da = <X_j, e> / <X_j, X_j>,   e <- e - X_j da,   a_j <- a_j + da
+// (Section 3 derives da as the one-column least-squares fit of e and the
+// update as the residual recursion e_{k+1} = e_k - X da_k).
+//
+// Data flow on the GPU.  The residual e never leaves registers: the rows of
+// the system are split over the threads of a "team" (a wave, a workgroup, or
+// every workgroup of a persistent grid), each thread owning R chunks of VEC
+// consecutive rows.  X is column-major and is streamed exactly once per sweep
+// with 128-bit loads; the columns of the next block are loaded while the
+// current block is being reduced, so the loads overlap the reduction.
+//
+// Columns are processed in blocks of B.  The team reduces the B dot products
+// <X_l, e> of a block (against the residual at the start of the block) plus
+// ||e||^2 in one round, then every thread recovers the exact sequential steps
+// of the block by forward substitution with the block's Gram entries
+//     da_l = (<X_l, e> - sum_{i<l} <X_l, X_i> da_i) / <X_l, X_l>,
+// which is algebraically identical to running the B steps one after another
+// (the residual after step i is e - sum_{i'<=i} X_i' da_i').  B = 1 is the
+// literal per-column reduction.  The axpy of block b is fused with the dots of
+// block b+1 in the same pass over the register-resident residual.
+//
+// The reduction of one block is: wave DPP sums -> LDS across the waves of a
+// workgroup -> (grid teams only) one 64-bit {sequence, value} word per value
+// and workgroup, published with a relaxed agent-scope atomic store and read
+// back by every workgroup, summed in a fixed order so all workgroups compute
+// bitwise identical da.
+#include "hpscd_device.hpp"
+#include "hpscd_internal.hpp"
+
+#include <float.h>
+
+namespace hpscd {
+
+// Coefficients of one block (B reciprocal norms, then the strictly-lower
+// Gram entries) are held one per lane across NCR registers and broadcast with
+// readlane when the block is solved.
+template <int B>
+struct Coef {
+  static constexpr int NG = B * (B - 1) / 2;
+  static constexpr int NGD = NG + B;
+  static constexpr int NCR = (NGD + WAVE - 1) / WAVE;
+  double v[NCR];
+
+  __device__ inline void load(const double* rdn, const double* gram, int64_t bi, int lane) {
+    // bi: block index within the sweep
+#pragma unroll
+    for (int r = 0; r < NCR; ++r) {
+      const int q = r * WAVE + lane;
+      double x = 0.0;
+      if (q < B) x = rdn[bi * B + q];
+      else if (q < NGD) x = gram[bi * NG + (q - B)];
+      v[r] = x;
+    }
+  }
+  __device__ inline double get(int q) const {  // q is a compile-time constant after unrolling
+    return readlane_f64(v[q / WAVE], q % WAVE);
+  }
+};
+
+template <int B>
+__device__ inline void forward_substitute(const double (&tot)[B + 1], const Coef<B>& cf, double (&da)[B]) {
+#pragma unroll
+  for (int l = 0; l < B; ++l) {
+    double acc = tot[l];
+#pragma unroll
+    for (int i = 0; i < l; ++i) acc -= cf.get(B + l * (l - 1) / 2 + i) * da[i];
+    da[l] = uniform_f64(acc * cf.get(l));
+  }
+}
+
+// --------------------------------------------------------------------------
+// Single-system kernel: a persistent grid (GRID) or one workgroup.
+// --------------------------------------------------------------------------
+template <class S, int T, int R, int B, bool GRID>
+__global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
+  using raw = typename S::raw_t;
+  constexpr int VEC = S::VEC;
+  constexpr int NW = T / WAVE;
+  constexpr int NV = B + 1;
+  constexpr int MAXC = 8;                       // up to 512 workgroups in a grid team
+  constexpr int MAXT = (NV * MAXC + NW - 1) / NW < 8 ? (NV * MAXC + NW - 1) / NW : 8;  // poll tasks per wave
+  __shared__ float red[2][NW][NV];
+  __shared__ double gsum[2][NV][MAXC];
+  __shared__ int sflag;
+
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+  const int wg = GRID ? (int)blockIdx.x : 0;
+  const int64_t m = A.m, n = A.n;
+  const int nb = (int)((n + B - 1) / B);
+  if (A.ctl[CTL_NONFINITE] != 0 || A.ctl[CTL_DONE] != 0) return;
+  if (tid == 0) sflag = 0;
+
+  float e[R][VEC];
+  int lim[R];
+  int64_t rof[R];
+  uint32_t boff[R];  // byte offset of the chunk inside a column (columns are < 4 GiB)
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    rof[c] = (int64_t)wg * (T * R * VEC) + (int64_t)VEC * (tid + T * c);
+    const int64_t left = m - rof[c];
+    lim[c] = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
+    boff[c] = (uint32_t)(rof[c] * (16 / VEC));
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? A.e0[rof[c] + i] : 0.f;
+  }
+
+  double prev_norm = A.fstat[1];
+  const double ynorm = sqrt(*A.ynorm2);
+  const int64_t nblocks = A.blk_end - A.blk_begin;
+  const int64_t col_bytes = A.ldx * (int64_t)(16 / VEC);
+  raw xa[B][R], xb[B][R];
+  Coef<B> ca, cb;
+
+  // Columns of one block are read through a buffer resource based at the
+  // block's first column: one 32-bit lane offset per chunk, one scalar offset
+  // per column, and loads past the last column of the system return zero.
+  auto load_block = [&](raw (&x)[B][R], Coef<B>& cf, int bi) {
+    const int j0 = bi * B;
+    const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
+    const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
+    const uint32_t nrec = span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char*>(reinterpret_cast<const char*>(A.X) + (int64_t)j0 * col_bytes), 0, (int)nrec, 0x00020000);
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (lim[c] > 0)
+          x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
+        else
+          x[l][c] = S::zero();
+      }
+    }
+    cf.load(A.rdn, A.gram, bi, lane);
+  };
+
+  auto finalize = [&](int sdone, bool conv, int64_t cols, double nrm2) {
+    if (wg == 0 && tid == 0) {
+      A.ctl[CTL_SWEEPS] = sdone;
+      A.ctl[CTL_CONVERGED] = conv ? 1 : 0;
+      A.ctl[CTL_DONE] = 1;
+      A.ctl64[C64_COLS] = cols;
+      A.fstat[0] = nrm2;
+    }
+  };
+
+  // Position of the current block: global index k, index in the sweep bi,
+  // complete sweeps before it sdone.
+  int bi = (int)(A.blk_begin % nb);
+  int sdone = (int)(A.blk_begin / nb);
+  uint32_t seq = (uint32_t)(A.blk_begin + 1);
+
+  // One block: returns true when the solve is over.
+  auto step = [&](raw (&cur)[B][R], raw (&nxt)[B][R], Coef<B>& ccur, Coef<B>& cnxt, bool has_next) -> bool {
+    const int j0 = bi * B;
+    const int nbi = (bi + 1 == nb) ? 0 : bi + 1;
+    if constexpr (!GRID) {
+      if (has_next) load_block(nxt, cnxt, nbi);
+    }
+
+    float p[NV];
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (lim[c] < VEC) cur[l][c] = mask_chunk<S>(cur[l][c], lim[c]);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(cur[l][c], i), e[c][i], acc);
+      }
+      p[l] = acc;
+    }
+    {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc = fmaf(e[c][i], e[c][i], acc);
+      p[B] = acc;
+    }
+    // Cancellation: workgroup 0 turns its norm partial into NaN at a sweep
+    // boundary, which every workgroup then sees in the reduced norm.
+    bool aborting = false;
+    if (bi == 0 && wg == 0 && tid == 0 && load_flag(&A.ctl[CTL_ABORT]) != 0) {
+      p[B] = __int_as_float(0x7fc00000);
+      aborting = true;
+    }
+
+    const int par = (int)(seq & 1u);
+#pragma unroll
+    for (int l = 0; l < NV; ++l) {
+      const float v = wave_sum(p[l]);
+      if (lane == 0) red[par][wave][l] = v;
+    }
+    __syncthreads();
+    double tot[NV];
+    if constexpr (GRID) {
+      // Slots are [parity][workgroup][value].  Poll task t covers value
+      // l = t / ncn of the 64 workgroups of chunk c = t % ncn; each wave
+      // issues all its task loads at once, then the next block's loads, then
+      // re-polls only words whose sequence number is not yet current.
+      uint64_t* slot_base = A.slots + (int64_t)par * NV * A.P;
+      if (tid < NV) {
+        float sacc = 0.f;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) sacc += red[par][w][tid];
+        publish(slot_base + (int64_t)wg * NV + tid, seq, sacc);
+      }
+      const int ncn = (A.P + WAVE - 1) / WAVE;
+      const int ntask = NV * ncn;
+      bool timed_out = false;
+      for (int t0 = wave; t0 < ntask; t0 += NW * MAXT) {
+        uint64_t w[MAXT];
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) {
+          const int t = t0 + q * NW;
+          const int l = t / ncn, c = t - l * ncn, idx = c * WAVE + lane;
+          const bool live = t < ntask && idx < A.P;
+          w[q] = live ? peek(slot_base + (int64_t)idx * NV + l) : ((uint64_t)seq << 32);
+        }
+        if (t0 == wave && has_next) load_block(nxt, cnxt, nbi);
+        uint64_t tstart = 0;
+        for (int spin = 0;; ++spin) {
+          bool ready = true;
+#pragma unroll
+          for (int q = 0; q < MAXT; ++q) ready = ready && ((uint32_t)(w[q] >> 32) == seq);
+          if (ready) break;
+          if (spin == 0) tstart = now_ticks();
+          else if (now_ticks() - tstart > A.timeout_ticks) {
+            timed_out = true;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+          for (int q = 0; q < MAXT; ++q) {
+            if ((uint32_t)(w[q] >> 32) != seq) {
+              const int t = t0 + q * NW;
+              const int l = t / ncn, c = t - l * ncn, idx = c * WAVE + lane;
+              w[q] = peek(slot_base + (int64_t)idx * NV + l);
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) {
+          const int t = t0 + q * NW;
+          if (t < ntask) {  // wave-uniform
+            const int l = t / ncn, c = t - l * ncn, idx = c * WAVE + lane;
+            const double v = wave_sum(idx < A.P ? (double)__uint_as_float((uint32_t)w[q]) : 0.0);
+            if (lane == 0) gsum[par][l][c] = v;
+          }
+        }
+      }
+      if (ntask <= wave && has_next) load_block(nxt, cnxt, nbi);
+      if (timed_out) sflag = 1;
+      __syncthreads();
+      if (sflag) {
+        if (tid == 0) store_flag(&A.ctl[CTL_ERR], ERR_TIMEOUT);
+        return true;
+      }
+#pragma unroll
+      for (int l = 0; l < NV; ++l) {
+        double sacc = 0.0;
+        for (int c = 0; c < ncn; ++c) sacc += gsum[par][l][c];
+        tot[l] = uniform_f64(sacc);
+      }
+    } else {
+#pragma unroll
+      for (int l = 0; l < NV; ++l) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) sacc += (double)red[par][w][l];
+        tot[l] = uniform_f64(sacc);
+      }
+    }
+
+    const double nrm2 = tot[B];
+    const double nrm = sqrt(nrm2);
+    if (!(nrm2 <= DBL_MAX)) {  // NaN or Inf: cancelled, or the data overflowed
+      if (wg == 0 && tid == 0) store_flag(&A.ctl[CTL_ERR], aborting ? ERR_ABORTED : ERR_NONFINITE);
+      finalize(sdone, false, (int64_t)sdone * n + j0, nrm2);
+      return true;
+    }
+    if (bi == 0) {
+      if (wg == 0 && tid == 0) { A.hist[sdone] = nrm; A.fstat[1] = nrm; }
+      bool stop = false, conv = false;
+      if (A.stop != STOP_NONE && nrm2 == 0.0) stop = conv = true;
+      else if (A.stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < A.tol * nrm) stop = conv = true;
+      else if (A.stop == STOP_REL_RESID && nrm < A.tol * ynorm) stop = conv = true;
+      if (!stop && sdone >= A.max_sweeps) stop = true;
+      prev_norm = nrm;
+      if (stop) { finalize(sdone, conv, (int64_t)sdone * n, nrm2); return true; }
+    } else if (A.check_cols > 0 && A.stop == STOP_REL_RESID) {
+      const int64_t cols = (int64_t)sdone * n + j0;
+      if (cols % A.check_cols == 0 && (nrm2 == 0.0 || nrm < A.tol * ynorm)) {
+        finalize(sdone, true, cols, nrm2);
+        return true;
+      }
+    }
+
+    double da[B];
+    forward_substitute<B>(tot, ccur, da);
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      const float f = (float)da[l];
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) e[c][i] = fmaf(-f, S::get(cur[l][c], i), e[c][i]);
+    }
+    // Every workgroup holds the same da; coefficient j is accumulated by
+    // workgroup j mod P (one writer per coefficient, no return value waited for).
+    if (tid < B) {
+      const int64_t j = j0 + tid;
+      if (j < n && (int)(j % A.P) == wg) {
+        double d = 0.0;
+#pragma unroll
+        for (int l = 0; l < B; ++l) if (tid == l) d = da[l];
+        (void)__hip_atomic_fetch_add(&A.a64[j], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    // advance to the next block
+    bi = nbi;
+    if (bi == 0) ++sdone;
+    ++seq;
+    return false;
+  };
+
+  if (nblocks > 0) load_block(xa, ca, bi);
+  __syncthreads();
+  for (int64_t k = 0; k < nblocks;) {
+    if (step(xa, xb, ca, cb, k + 1 < nblocks)) break;
+    if (++k >= nblocks) break;
+    if (step(xb, xa, cb, ca, k + 1 < nblocks)) break;
+    ++k;
+  }
+#pragma unroll
+  for (int c = 0; c < R; ++c)
+#pragma unroll
+    for (int i = 0; i < VEC; ++i)
+      if (i < lim[c]) A.e_out[rof[c] + i] = e[c][i];
+}
+
+// --------------------------------------------------------------------------
+// Batched kernel: a persistent grid of workgroups pulls work items from an
+// atomic queue.  An item is either one system solved by the whole workgroup
+// (rows over T threads, reductions through LDS) or up to NW systems solved
+// by one wave each (rows over 64 lanes, reductions by DPP only, no barrier).
+// --------------------------------------------------------------------------
+constexpr int BT = 256;     // threads per batched workgroup
+constexpr int BR = 8;       // FP32 chunks per thread: 8192 rows per workgroup, 2048 per wave
+
+template <int TT, int R, int B>
+__device__ inline void team_solve(const BatchArgs& A, int sidx, int ttid, float (&red)[2][BT / WAVE][B + 1]) {
+  using S = F32;
+  using raw = S::raw_t;
+  constexpr int VEC = S::VEC;
+  constexpr int NW = TT / WAVE;
+  constexpr int NV = B + 1;
+  const int lane = ttid & (WAVE - 1), wave = ttid / WAVE;
+  const SysDesc sd = A.sys[sidx];
+  const int64_t m = sd.m, n = sd.n, nb = (n + B - 1) / B;
+  const float* X = A.Xpool + sd.x_off;
+  const double* rdn = A.rdn + sd.g_off;
+  const double* gram = A.gram + sd.g_off / B * Coef<B>::NG;
+  double* hist = A.hist + sd.h_off;
+
+  float e[R][VEC];
+  int lim[R];
+  int64_t rof[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    rof[c] = (int64_t)VEC * (ttid + TT * c);
+    const int64_t left = m - rof[c];
+    lim[c] = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? A.e0pool[sd.y_off + rof[c] + i] : 0.f;
+  }
+  const double ynorm = sqrt(A.ynorm2[sidx]);
+  double prev_norm = 0.0;
+  const int64_t ke = (int64_t)A.max_sweeps * nb + 1;
+  raw xa[B][R], xb[B][R];
+  Coef<B> ca, cb;
+
+  auto load_block = [&](raw (&x)[B][R], Coef<B>& cf, int64_t k) {
+    const int64_t bi = k % nb, j0 = bi * B;
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      const int64_t j = j0 + l;
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (j < n && lim[c] > 0) x[l][c] = load_chunk<S>(X, j * sd.ldx + rof[c]);
+        else x[l][c] = S::zero();
+      }
+    }
+    cf.load(rdn, gram, bi, lane);
+  };
+
+  auto step = [&](raw (&cur)[B][R], raw (&nxt)[B][R], Coef<B>& ccur, Coef<B>& cnxt, int64_t k) -> bool {
+    const int64_t bi = k % nb, j0 = bi * B;
+    const int sdone = (int)(k / nb);
+    if (k + 1 < ke) load_block(nxt, cnxt, k + 1);
+    float p[NV];
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (lim[c] < VEC) cur[l][c] = mask_chunk<S>(cur[l][c], lim[c]);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(cur[l][c], i), e[c][i], acc);
+      }
+      p[l] = acc;
+    }
+    {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc = fmaf(e[c][i], e[c][i], acc);
+      p[B] = acc;
+    }
+    double tot[NV];
+    if constexpr (NW == 1) {
+#pragma unroll
+      for (int l = 0; l < NV; ++l) tot[l] = uniform_f64((double)wave_sum(p[l]));
+    } else {
+      const int par = (int)(k & 1);
+#pragma unroll
+      for (int l = 0; l < NV; ++l) {
+        const float v = wave_sum(p[l]);
+        if (lane == 0) red[par][wave][l] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int l = 0; l < NV; ++l) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += (double)red[par][w][l];
+        tot[l] = uniform_f64(s);
+      }
+    }
+    const double nrm2 = tot[B], nrm = sqrt(nrm2);
+    if (bi == 0) {
+      if (ttid == 0) hist[sdone] = nrm;
+      bool stop = false, conv = false;
+      if (!(nrm2 <= DBL_MAX)) stop = true;
+      else if (A.stop != STOP_NONE && nrm2 == 0.0) stop = conv = true;
+      else if (A.stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < A.tol * nrm) stop = conv = true;
+      else if (A.stop == STOP_REL_RESID && nrm < A.tol * ynorm) stop = conv = true;
+      if (!stop && sdone >= A.max_sweeps) stop = true;
+      prev_norm = nrm;
+      if (stop) {
+        if (ttid == 0) { A.sweeps[sidx] = sdone; A.converged[sidx] = conv ? 1 : 0; }
+        return true;
+      }
+    }
+    double da[B];
+    forward_substitute<B>(tot, ccur, da);
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      const float f = (float)da[l];
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) e[c][i] = fmaf(-f, S::get(cur[l][c], i), e[c][i]);
+    }
+    if (ttid < B) {
+      double d = 0.0;
+#pragma unroll
+      for (int l = 0; l < B; ++l) if (ttid == l) d = da[l];
+      if (j0 + ttid < n) {
+        // only this lane touches a_j of this system; no return value is waited for
+        (void)__hip_atomic_fetch_add(A.a64pool + sd.a_off + j0 + ttid, d, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    return false;
+  };
+
+  load_block(xa, ca, 0);
+  for (int64_t k = 0; k < ke;) {
+    if (step(xa, xb, ca, cb, k)) break;
+    if (++k >= ke) break;
+    if (step(xb, xa, cb, ca, k)) break;
+    ++k;
+  }
+}
+
+template <int B>
+__global__ void __launch_bounds__(BT) k_batched(BatchArgs A) {
+  constexpr int NW = BT / WAVE;
+  __shared__ float red[2][NW][B + 1];
+  __shared__ int s_item;
+  const int tid = threadIdx.x, wave = tid / WAVE;
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(A.queue, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= A.nitems) break;
+    const WorkItem w = A.items[it];
+    if (w.mode == 0) {
+      team_solve<BT, BR, B>(A, w.sys[0], tid, red);
+    } else if (wave < w.count) {
+      team_solve<WAVE, BR, B>(A, w.sys[wave], tid & (WAVE - 1), red);
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Variant registry
+// --------------------------------------------------------------------------
+#define HPSCD_SWEEP_VARIANTS(X_)                                                  \
+  X_(F32, 1024, 1, 1, true) X_(F32, 1024, 1, 2, true) X_(F32, 1024, 1, 4, true)   \
+  X_(F32, 1024, 1, 8, true)                                                       \
+  X_(F32, 512, 2, 2, true) X_(F32, 512, 2, 4, true) X_(F32, 512, 2, 8, true)      \
+  X_(BF16, 512, 1, 4, true) X_(BF16, 512, 1, 8, true) X_(BF16, 1024, 1, 4, true)  \
+  X_(F32, 256, 1, 1, true) X_(F32, 256, 1, 2, true) X_(F32, 256, 1, 4, true)      \
+  X_(F32, 256, 1, 8, true)                                                         \
+  X_(F32, 256, 2, 1, false) X_(F32, 256, 2, 2, false) X_(F32, 256, 2, 4, false)   \
+  X_(F32, 256, 2, 8, false)                                                        \
+  X_(F32, 256, 4, 1, false) X_(F32, 256, 4, 2, false) X_(F32, 256, 4, 4, false)   \
+  X_(F32, 256, 4, 8, false)                                                        \
+  X_(BF16, 1024, 1, 1, true) X_(BF16, 1024, 1, 8, true)                           \
+  X_(BF16, 256, 1, 1, false) X_(BF16, 256, 1, 4, false) X_(BF16, 256, 1, 8, false)\
+  X_(BF16, 256, 2, 1, false) X_(BF16, 256, 2, 4, false) X_(BF16, 256, 2, 8, false)
+
+#define HPSCD_IS_BF16_F32 false
+#define HPSCD_IS_BF16_BF16 true
+
+struct Variant {
+  int T, R, B;
+  bool bf16, grid;
+  const void* fn;
+};
+
+#define HPSCD_ENTRY(S, T, R, B, G) \
+  {T, R, B, HPSCD_IS_BF16_##S, G, reinterpret_cast<const void*>(&k_sweep<S, T, R, B, G>)},
+static const Variant kVariants[] = {HPSCD_SWEEP_VARIANTS(HPSCD_ENTRY)};
+
+static const Variant* find_variant(int T, int R, int B, bool bf16, bool grid) {
+  for (const Variant& v : kVariants)
+    if (v.T == T && v.R == R && v.B == B && v.bf16 == bf16 && v.grid == grid) return &v;
+  return nullptr;
+}
+
+bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid) {
+  return find_variant(T, R, B, bf16, grid) != nullptr;
+}
+
+int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid) {
+  const Variant* v = find_variant(T, R, B, bf16, grid);
+  if (!v) return 0;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn, T, 0) != hipSuccess) return 0;
+  return nb;
+}
+
+hipError_t launch_sweep(int T, int R, int B, bool bf16, bool grid, const SolveArgs& a, hipStream_t s,
+                        bool cooperative) {
+  const Variant* v = find_variant(T, R, B, bf16, grid);
+  if (!v) return hipErrorInvalidValue;
+  SolveArgs args = a;
+  void* kargs[] = {&args};
+  const dim3 g(grid ? (unsigned)a.P : 1u), b((unsigned)T);
+  if (cooperative) return hipLaunchCooperativeKernel(v->fn, g, b, kargs, 0, s);
+  return hipLaunchKernel(v->fn, g, b, kargs, 0, s);
+}
+
+#define HPSCD_BATCHED_VARIANTS(X_) X_(1) X_(2) X_(4)
+struct BVariant { int B; const void* fn; };
+#define HPSCD_BENTRY(B) {B, reinterpret_cast<const void*>(&k_batched<B>)},
+static const BVariant kBVariants[] = {HPSCD_BATCHED_VARIANTS(HPSCD_BENTRY)};
+
+static const BVariant* find_bvariant(int B) {
+  for (const BVariant& v : kBVariants) if (v.B == B) return &v;
+  return nullptr;
+}
+bool batched_variant_exists(int B) { return find_bvariant(B) != nullptr; }
+int batched_threads() { return BT; }
+int batched_rows_per_wave() { return WAVE * BR * F32::VEC; }
+int batched_rows_per_wg() { return BT * BR * F32::VEC; }
+int batched_max_blocks_per_cu(int B) {
+  const BVariant* v = find_bvariant(B);
+  if (!v) return 0;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn, BT, 0) != hipSuccess) return 0;
+  return nb;
+}
+hipError_t launch_batched(int B, const BatchArgs& a, int grid, hipStream_t s) {
+  const BVariant* v = find_bvariant(B);
+  if (!v) return hipErrorInvalidValue;
+  BatchArgs args = a;
+  void* kargs[] = {&args};
+  return hipLaunchKernel(v->fn, dim3((unsigned)grid), dim3(BT), kargs, 0, s);
+}
+
+}  // namespace hpscd

@@ -1,0 +1,301 @@
+"""Python binding of libhpscd (ctypes).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels
+of ``libhpscd.so``.  PyTorch supplies device memory and the current stream.
+Importing this module fails loudly when the library has not been built.
+
+Layout: a system's X is passed as a torch tensor ``Xt`` of shape ``(n, ldx)``
+(C-contiguous), i.e. column-major X with column j in ``Xt[j, :m]``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+# torch's HIP runtime must be loaded before the library: libhpscd.so then binds
+# to that same runtime (same SONAME), so torch's allocations and stream handles
+# are valid in every call.  Loading the library first would map a second HIP
+# runtime into the process.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libhpscd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2104_12570_amd.build` "
+        "(there is no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+def hip_runtimes_mapped():
+    """Distinct HIP runtime files mapped into this process (expected: one)."""
+    with open("/proc/self/maps") as f:
+        return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln})
+
+
+if len(hip_runtimes_mapped()) != 1:
+    raise ImportError(f"expected one HIP runtime in the process, found {hip_runtimes_mapped()}")
+
+STOP_NONE, STOP_REL_CHANGE, STOP_REL_RESID = 0, 1, 2
+F_NO_FINAL_CHECK, F_FORCE_GRID, F_FORCE_WG, F_NO_COOP = 1, 2, 4, 8
+
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EABORTED, ETIMEOUT = range(7)
+_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENONFINITE", 5: "EABORTED", 6: "ETIMEOUT"}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("max_sweeps", ctypes.c_int32), ("stop", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("check_cols", ctypes.c_int64), ("refresh_cols", ctypes.c_int64), ("block", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("team_threads", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("sweeps_done", ctypes.c_int32), ("converged", ctypes.c_int32), ("cols_done", ctypes.c_int64),
+                ("zero_cols", ctypes.c_int64), ("final_norm", ctypes.c_double),
+                ("final_rel_resid", ctypes.c_double), ("y_norm", ctypes.c_double),
+                ("block_used", ctypes.c_int32), ("team_wgs", ctypes.c_int32), ("team_threads", ctypes.c_int32),
+                ("refreshes", ctypes.c_int32), ("sweep_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Sys(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("x_off", ctypes.c_int64),
+                ("ldx", ctypes.c_int64), ("y_off", ctypes.c_int64), ("a_off", ctypes.c_int64)]
+
+
+_vp, _i64, _i32, _dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
+_OP, _IP = ctypes.POINTER(Opts), ctypes.POINTER(Info)
+
+_SIGS = {
+    "hpscd_version": (ctypes.c_int, []),
+    "hpscd_last_error": (ctypes.c_char_p, []),
+    "hpscd_default_opts": (None, [_OP]),
+    "hpscd_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp)]),
+    "hpscd_destroy": (None, [_vp]),
+    "hpscd_validate": (ctypes.c_int, [_i64, _i64, _vp, _i64, ctypes.c_int, _vp, _OP, _vp]),
+    "hpscd_solve_f32": (ctypes.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _OP, _vp, _dp, _IP, _vp]),
+    "hpscd_solve_bf16": (ctypes.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _OP, _vp, _dp, _IP, _vp]),
+    "hpscd_convert_bf16": (ctypes.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _i64, _vp]),
+    "hpscd_residual_f64": (ctypes.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _dp, _vp]),
+    "hpscd_solve_batched_f32": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Sys), _vp, _vp, _vp, _OP, _vp, _dp,
+                                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                               _dp, _IP, _vp]),
+    "hpscd_autotune_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Sys), _vp, _vp, _OP, _vp, _vp]),
+    "hpscd_abort": (ctypes.c_int, [_vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+class HPSCDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(st):
+    if st != OK:
+        raise HPSCDError(st, _lib.hpscd_last_error().decode())
+
+
+def last_error() -> str:
+    return _lib.hpscd_last_error().decode()
+
+
+def make_opts(max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols=0, refresh_cols=0, block=0, flags=0,
+              team_threads=0) -> Opts:
+    o = Opts()
+    _lib.hpscd_default_opts(ctypes.byref(o))
+    o.max_sweeps, o.stop, o.tol = int(max_sweeps), int(stop), float(tol)
+    o.check_cols, o.refresh_cols, o.block, o.flags = int(check_cols), int(refresh_cols), int(block), int(flags)
+    o.team_threads = int(team_threads)
+    return o
+
+
+def validate(m, n, X_ptr, ldx, elem_bytes, y_ptr, opts: Opts, a_ptr) -> int:
+    """Host-only argument check (no device needed); returns the status code."""
+    return _lib.hpscd_validate(m, n, X_ptr, ldx, elem_bytes, y_ptr, ctypes.byref(opts), a_ptr)
+
+
+# --------------------------------------------------------------- device side
+_CTX = {}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def context(device: int | None = None):
+    torch = _torch()
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _CTX:
+        h = _vp()
+        _check(_lib.hpscd_create(dev, ctypes.byref(h)))
+        _CTX[dev] = h
+    return _CTX[dev]
+
+
+def _stream():
+    return _vp(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return _vp(t.data_ptr()) if t is not None else _vp(0)
+
+
+def _need_cuda(t, name, dtype=None):
+    torch = _torch()
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+@dataclass
+class Result:
+    a: object          # torch tensor (n,) float32
+    hist: np.ndarray   # ||e|| after sweeps 0..sweeps_done
+    info: dict
+
+
+def solve(Xt, y, a0=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols=0, block=0, flags=0,
+          team_threads=0, want_hist=True) -> Result:
+    """Solve X·a = y (Algorithm 1, single precision) on the GPU.
+
+    Xt: (n, ldx) float32 CUDA tensor (column j of X in Xt[j, :m]); y: (m,)."""
+    torch = _torch()
+    _need_cuda(Xt, "Xt", torch.float32)
+    _need_cuda(y, "y", torch.float32)
+    _need_cuda(a0, "a0", torch.float32)
+    n, ldx = Xt.shape
+    m = y.numel()
+    a = torch.empty(n, dtype=torch.float32, device=Xt.device)
+    opts = make_opts(max_sweeps, stop, tol, check_cols, 0, block, flags, team_threads)
+    hist = np.full(max_sweeps + 1, np.nan) if want_hist else None
+    info = Info()
+    _check(_lib.hpscd_solve_f32(context(Xt.device.index), m, n, _ptr(Xt), ldx, _ptr(y), _ptr(a0),
+                                ctypes.byref(opts), _ptr(a),
+                                hist.ctypes.data_as(_dp) if hist is not None else None,
+                                ctypes.byref(info), _stream()))
+    h = hist[: info.sweeps_done + 1] if hist is not None else None
+    return Result(a, h, info.as_dict())
+
+
+def convert_bf16(Xt):
+    """bfloat16 copy of X (round to nearest even), shape (n, ldx rounded up to 8)."""
+    torch = _torch()
+    _need_cuda(Xt, "Xt", torch.float32)
+    n, ldx = Xt.shape
+    ldd = (ldx + 7) // 8 * 8
+    out = torch.empty((n, ldd), dtype=torch.bfloat16, device=Xt.device)
+    _check(_lib.hpscd_convert_bf16(context(Xt.device.index), ldx, n, _ptr(Xt), ldx, _ptr(out), ldd, _stream()))
+    return out
+
+
+def solve_bf16(Xb, Xt32, y, a0=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols=0, refresh_cols=0,
+               block=0, flags=0, want_hist=True) -> Result:
+    """bfloat16-storage form: sweeps read Xb, refreshes and the final check read Xt32."""
+    torch = _torch()
+    _need_cuda(Xb, "Xb", torch.bfloat16)
+    _need_cuda(Xt32, "Xt32", torch.float32)
+    _need_cuda(y, "y", torch.float32)
+    _need_cuda(a0, "a0", torch.float32)
+    n, ldxb = Xb.shape
+    ldx = Xt32.shape[1]
+    m = y.numel()
+    a = torch.empty(n, dtype=torch.float32, device=Xb.device)
+    opts = make_opts(max_sweeps, stop, tol, check_cols, refresh_cols, block, flags)
+    hist = np.full(max_sweeps + 1, np.nan) if want_hist else None
+    info = Info()
+    _check(_lib.hpscd_solve_bf16(context(Xb.device.index), m, n, _ptr(Xb), ldxb, _ptr(Xt32), ldx, _ptr(y),
+                                 _ptr(a0), ctypes.byref(opts), _ptr(a),
+                                 hist.ctypes.data_as(_dp) if hist is not None else None,
+                                 ctypes.byref(info), _stream()))
+    h = hist[: info.sweeps_done + 1] if hist is not None else None
+    return Result(a, h, info.as_dict())
+
+
+def residual_f64(Xt, y, a, want_e=False):
+    """r = y - X·a with FP64 sums; returns (||r||_2, r as float32 or None)."""
+    torch = _torch()
+    _need_cuda(Xt, "Xt", torch.float32)
+    n, ldx = Xt.shape
+    m = y.numel()
+    e = torch.empty(m, dtype=torch.float32, device=Xt.device) if want_e else None
+    nrm = ctypes.c_double()
+    _check(_lib.hpscd_residual_f64(context(Xt.device.index), m, n, _ptr(Xt), ldx, _ptr(y), _ptr(a), _ptr(e),
+                                   ctypes.byref(nrm), _stream()))
+    return nrm.value, e
+
+
+def _sys_array(table):
+    table = np.asarray(table, dtype=np.int64).reshape(-1, 6)
+    arr = (Sys * len(table))()
+    for i, row in enumerate(table):
+        arr[i] = Sys(*[int(v) for v in row])
+    return arr
+
+
+@dataclass
+class BatchResult:
+    a: object
+    hist: np.ndarray | None
+    sweeps: np.ndarray
+    converged: np.ndarray
+    final_rel_resid: np.ndarray
+    info: dict
+
+
+def solve_batched(Xpool, ypool, table, a0pool=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, block=0,
+                  flags=0, a_size=None, want_hist=False) -> BatchResult:
+    """Solve every system of a packed batch in one persistent launch.
+    ``table[i] = (m, n, x_off, ldx, y_off, a_off)``."""
+    torch = _torch()
+    _need_cuda(Xpool, "Xpool", torch.float32)
+    _need_cuda(ypool, "ypool", torch.float32)
+    _need_cuda(a0pool, "a0pool", torch.float32)
+    table = np.asarray(table, dtype=np.int64).reshape(-1, 6)
+    count = len(table)
+    if a_size is None:
+        a_size = int((table[:, 5] + table[:, 1]).max())
+    a = torch.zeros(a_size, dtype=torch.float32, device=Xpool.device)
+    opts = make_opts(max_sweeps, stop, tol, 0, 0, block, flags)
+    hist = np.full((count, max_sweeps + 1), np.nan) if want_hist else None
+    sw = np.zeros(count, np.int32)
+    cv = np.zeros(count, np.int32)
+    fr = np.zeros(count)
+    info = Info()
+    _check(_lib.hpscd_solve_batched_f32(
+        context(Xpool.device.index), count, _sys_array(table), _ptr(Xpool), _ptr(ypool), _ptr(a0pool),
+        ctypes.byref(opts), _ptr(a), hist.ctypes.data_as(_dp) if hist is not None else None,
+        sw.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        fr.ctypes.data_as(_dp), ctypes.byref(info), _stream()))
+    return BatchResult(a, hist, sw, cv, fr, info.as_dict())
+
+
+def autotune_batched(Xpool, ypool, table, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, a_size=None):
+    torch = _torch()
+    table = np.asarray(table, dtype=np.int64).reshape(-1, 6)
+    if a_size is None:
+        a_size = int((table[:, 5] + table[:, 1]).max())
+    a = torch.zeros(a_size, dtype=torch.float32, device=Xpool.device)
+    opts = make_opts(max_sweeps, stop, tol)
+    _check(_lib.hpscd_autotune_batched(context(Xpool.device.index), len(table), _sys_array(table), _ptr(Xpool),
+                                       _ptr(ypool), ctypes.byref(opts), _ptr(a), _stream()))
+
+
+def abort(device: int | None = None):
+    _check(_lib.hpscd_abort(context(device)))

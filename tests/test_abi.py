@@ -1,0 +1,129 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point that include/hpscd.h declares, its struct layouts match the
+header, and arguments are rejected before any device work."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hpscd.h")
+
+
+@pytest.fixture(scope="module")
+def hp():
+    from paper_2104_12570_amd import hpscd
+    return hpscd
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hpscd_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(hp):
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(hp._lib, name), name
+    nm = subprocess.run(["nm", "-D", "--defined-only", hp.LIB_PATH], capture_output=True, text=True).stdout
+    for name in names:
+        assert re.search(rf"\bT {name}\b", nm), f"{name} not exported"
+
+
+def test_struct_layouts_match_header(hp):
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "hpscd.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(hpscd_opts), sizeof(hpscd_info), sizeof(hpscd_sys),
+         offsetof(hpscd_opts, tol), offsetof(hpscd_info, final_norm), offsetof(hpscd_info, total_ms));
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == [ctypes.sizeof(hp.Opts), ctypes.sizeof(hp.Info), ctypes.sizeof(hp.Sys),
+                   hp.Opts.tol.offset, hp.Info.final_norm.offset, hp.Info.total_ms.offset]
+
+
+def test_version(hp):
+    assert hp._lib.hpscd_version() == 1
+
+
+@pytest.mark.parametrize("case,msg", [
+    (dict(m=0), "m must be"),
+    (dict(n=0), "n must be"),
+    (dict(X=0), "X is NULL"),
+    (dict(y=0), "y is NULL"),
+    (dict(a=0), "a_out is NULL"),
+    (dict(ldx=50), "ldx"),
+    (dict(ldx=102), "multiple of 4"),
+    (dict(X=8), "16-byte aligned"),
+    (dict(elem=2, ldx=100), "multiple of 8"),
+    (dict(max_sweeps=-1), "max_sweeps"),
+    (dict(stop=7), "stop rule"),
+    (dict(tol=float("nan")), "tol"),
+    (dict(tol=-1.0), "tol"),
+    (dict(block=3), "block"),
+    (dict(flags=2 | 4), "exclusive"),
+])
+def test_validation_rejects(hp, case, msg):
+    kw = dict(m=100, n=10, X=4096, ldx=100, elem=4, y=64, a=128, max_sweeps=5, stop=0, tol=0.0, block=0, flags=0)
+    kw.update(case)
+    o = hp.make_opts(kw["max_sweeps"], kw["stop"], kw["tol"], 0, 0, kw["block"], kw["flags"])
+    st = hp.validate(kw["m"], kw["n"], kw["X"], kw["ldx"], kw["elem"], kw["y"], o, kw["a"])
+    assert st == hp.EINVAL
+    assert msg in hp.last_error()
+
+
+def test_validation_accepts(hp):
+    o = hp.make_opts(5)
+    assert hp.validate(100, 10, 4096, 100, 4, 64, o, 128) == hp.OK
+    assert hp.validate(100, 10, 4096, 104, 2, 64, o, 128) == hp.OK
+
+
+def test_null_context_rejected(hp):
+    o = hp.make_opts(5)
+    st = hp._lib.hpscd_solve_f32(None, 100, 10, 4096, 100, 64, None, ctypes.byref(o), 128, None, None, None)
+    assert st == hp.EINVAL and "ctx" in hp.last_error()
+    st = hp._lib.hpscd_solve_batched_f32(None, 0, None, 16, 16, None, ctypes.byref(o), 16, None, None, None,
+                                         None, None, None)
+    assert st == hp.EINVAL
+
+
+def test_batch_validation(hp):
+    o = hp.make_opts(5)
+    table = hp._sys_array([[9000, 10, 0, 9000, 0, 0]])
+    st = hp._lib.hpscd_solve_batched_f32(None, 1, table, 4096, 64, None, ctypes.byref(o), 128, None, None, None,
+                                         None, None, None)
+    assert st == hp.EINVAL and "exceeds" in hp.last_error()
+    table = hp._sys_array([[100, 10, 2, 100, 0, 0]])
+    st = hp._lib.hpscd_solve_batched_f32(None, 1, table, 4096, 64, None, ctypes.byref(o), 128, None, None, None,
+                                         None, None, None)
+    assert st == hp.EINVAL and "x_off" in hp.last_error()
+
+
+def test_create_without_device(hp):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert hp._lib.hpscd_create(0, ctypes.byref(h)) == hp.EDEVICE
+
+
+def test_single_hip_runtime_shared_with_torch(hp):
+    """The library binds to the HIP runtime torch loaded (one runtime per process)."""
+    import torch
+    maps = hp.hip_runtimes_mapped()
+    assert len(maps) == 1
+    assert os.path.dirname(torch.__file__) in maps[0]

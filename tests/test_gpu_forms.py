@@ -1,0 +1,125 @@
+"""GPU parity of the bfloat16-storage form and of the batched form."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import hpscd_oracle as ho
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+# ---------------------------------------------------------------- bfloat16
+
+def test_convert_bf16_bitwise(lib):
+    """GPU rounding to bfloat16 equals the oracle's (and torch's) on every value."""
+    import torch
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(5000), rng.standard_normal(500) * 1e-39,
+                        rng.standard_normal(500) * 1e37, [0.0, -0.0, np.inf, -np.inf]]).astype(np.float32)
+    u = x.view(np.uint32)
+    ties = ((u & np.uint32(0xFFFF0000)) | np.uint32(0x8000)).view(np.float32)
+    x = np.concatenate([x, ties[:1000]])
+    n = 7
+    m = len(x) // n
+    Xt = np.zeros((n, gen.round_up(m, 8)), np.float32)
+    Xt[:, :m] = x[: n * m].reshape(n, m)
+    got = lib.convert_bf16(dev(Xt)).view(torch.int16).cpu().numpy().view(np.uint16)
+    ref = (ho.bf16_round(Xt).view(np.uint32) >> 16).astype(np.uint16)
+    assert np.array_equal(got[:, :m], ref[:, :m])
+
+
+@pytest.mark.parametrize("team", ["wg", "grid"])
+def test_bf16_form_matches_oracle(lib, team):
+    """The storage form against the oracle of the same form (Algorithm 1 on
+    bfloat16-rounded X, residual refreshed from FP32 X every refresh_cols
+    column steps) at equal sweeps."""
+    if team == "wg":
+        s = gen.wide(m=2000, n=8000, seed=5)
+        flags, refresh, sweeps = lib.F_FORCE_WG, 4000, 3
+    else:
+        s = gen.tall_large(m=100_000, n=32, seed=9)
+        flags, refresh, sweeps = lib.F_FORCE_GRID, 32, 4
+    say("bf16", team)
+    X32 = dev(s.Xt)
+    Xb = lib.convert_bf16(X32)
+    r = lib.solve_bf16(Xb, X32, dev(s.y), max_sweeps=sweeps, refresh_cols=refresh, flags=flags)
+    ref = oracle.solve_bf16_refresh(s.Xt, s.y, s.m, max_sweeps=sweeps, refresh_cols=refresh)
+    assert r.info["refreshes"] >= 1
+    assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5, r.info
+    assert np.all(np.abs(np.asarray(r.hist) - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0])
+    fr = oracle.final_rel_resid(s.Xt, s.y, s.m, ref.a)
+    assert r.info["final_rel_resid"] == pytest.approx(fr, rel=1e-3, abs=1e-7)
+
+
+def test_bf16_no_refresh_error_bound(lib):
+    """Without refresh the error against the FP32 problem is that of the
+    rounded matrix: stated per result, here bounded by 2^-7 relative in a."""
+    s = gen.tall_small()
+    X32 = dev(s.Xt)
+    r = lib.solve_bf16(lib.convert_bf16(X32), X32, dev(s.y), max_sweeps=100)
+    ref32 = oracle.solve(s.Xt, s.y, s.m, max_sweeps=100)
+    refb = oracle.solve_bf16_refresh(s.Xt, s.y, s.m, max_sweeps=100)
+    assert rel(r.a.cpu().numpy(), refb.a) <= 1e-5
+    assert rel(r.a.cpu().numpy(), ref32.a) <= 2.0 ** -7
+
+
+# ---------------------------------------------------------------- batched
+
+@pytest.mark.parametrize("block", [1, 2, 4])
+def test_batched_matches_oracle(lib, block):
+    b = gen.batch(seed=4, count=40, m_lo=100, m_hi=8192, n_lo=3, n_hi=128, pad=np.nan)
+    say("batched", block, b.count)
+    r = lib.solve_batched(dev(b.Xpool), dev(b.ypool), b.table, max_sweeps=12, block=block, want_hist=True)
+    a = r.a.cpu().numpy()
+    refs = oracle.solve_batch(b, max_sweeps=12)
+    for i, ref in enumerate(refs):
+        m, n, _, _, _, ao = b.table[i]
+        assert rel(a[ao: ao + n], ref.a) <= 1e-5, (i, m, n)
+        assert r.sweeps[i] == 12
+        assert np.all(np.abs(r.hist[i] - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0])
+        fr = oracle.final_rel_resid(b.system(i).Xt, b.system(i).y, m, ref.a)
+        assert r.final_rel_resid[i] == pytest.approx(fr, rel=1e-3, abs=1e-7)
+
+
+def test_batched_equals_single(lib):
+    b = gen.batch(seed=6, count=16, m_lo=256, m_hi=8192, n_lo=8, n_hi=64)
+    r = lib.solve_batched(dev(b.Xpool), dev(b.ypool), b.table, max_sweeps=8)
+    a = r.a.cpu().numpy()
+    for i in range(b.count):
+        s = b.system(i)
+        one = lib.solve(dev(s.Xt), dev(s.y), max_sweeps=8).a.cpu().numpy()
+        ao = b.table[i, 5]
+        assert rel(a[ao: ao + s.n], one) <= 1e-5
+
+
+def test_batched_stop_and_warm_start(lib):
+    b = gen.batch(seed=8, count=24, m_lo=256, m_hi=4096, n_lo=8, n_hi=64)
+    say("batched stop")
+    r = lib.solve_batched(dev(b.Xpool), dev(b.ypool), b.table, max_sweeps=200,
+                          stop=lib.STOP_REL_CHANGE, tol=1e-6)
+    refs = oracle.solve_batch(b, max_sweeps=200, tol=1e-6, stop=oracle.STOP_REL_CHANGE)
+    agree = sum(int(r.sweeps[i] == refs[i].sweeps) for i in range(b.count))
+    assert agree >= b.count - 2          # a sweep count may differ right at the threshold
+    assert np.all(r.converged == 1)
+    # warm start from the converged answer: the residual does not grow
+    a0 = r.a.clone()
+    r2 = lib.solve_batched(dev(b.Xpool), dev(b.ypool), b.table, a0pool=a0, max_sweeps=1, want_hist=True)
+    for i in range(b.count):
+        assert r2.hist[i][1] <= r2.hist[i][0] * (1 + 1e-6)

@@ -1,0 +1,215 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs, after the same number of sweeps.
+
+Tolerance for single precision: ||a_gpu - a_oracle|| / ||a_oracle|| <= 1e-5
+and every hist entry within 1e-5·hist[0], the oracle running on the FP32
+input values.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+TOL_A = 1e-5
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def run(lib, s, sweeps, **kw):
+    r = lib.solve(dev(s.Xt), dev(s.y), **({"a0": dev(kw.pop("a0"))} if "a0" in kw else {}), max_sweeps=sweeps, **kw)
+    return r
+
+
+def check(lib, s, sweeps, tol=TOL_A, **kw):
+    a0 = kw.get("a0")
+    r = run(lib, s, sweeps, **kw)
+    ref = oracle.solve(s.Xt, s.y, s.m, a0=a0, max_sweeps=sweeps)
+    a = r.a.cpu().numpy()
+    e = rel(a, ref.a)
+    assert e <= tol, (e, r.info)
+    h = np.asarray(r.hist)
+    assert len(h) == sweeps + 1
+    assert np.all(np.abs(h - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0]), (h[:4], ref.hist[:4])
+    return r, ref
+
+
+# ------------------------------------------------------------ exact cases
+
+@pytest.mark.parametrize("flags", [0, 2])       # one workgroup / persistent grid
+@pytest.mark.parametrize("block", [1, 2])
+def test_dyadic_2x2_bitwise(lib, flags, block):
+    """Closed form of Algorithm 1 on X = [[1,1],[0,1]], y = (2,1): all values
+    dyadic, so the single-precision GPU result is exact."""
+    say("dyadic", flags, block)
+    Xt = np.zeros((2, 4), np.float32)
+    Xt[0, :2] = [1, 0]
+    Xt[1, :2] = [1, 1]
+    Xt[:, 2:] = np.nan                             # padding rows are never read
+    y = np.array([2, 1], np.float32)
+    for s in (1, 2, 5, 12):
+        r = lib.solve(dev(Xt), dev(y), max_sweeps=s, block=block, flags=flags)
+        assert r.a.cpu().numpy().tolist() == [1 + 2.0 ** (1 - s), 1 - 2.0 ** (-s)]
+        assert r.hist[-1] == math.sqrt(2.0) * 2.0 ** -s
+
+
+# ------------------------------------------------------------ tall small
+
+@pytest.mark.parametrize("team", ["wg", "grid"])
+@pytest.mark.parametrize("block", [1, 4, 8])
+def test_tall_small_200_sweeps(lib, team, block):
+    s = gen.tall_small(pad=np.nan)
+    flags = lib.F_FORCE_WG if team == "wg" else lib.F_FORCE_GRID
+    say("tall_small", team, block)
+    r, ref = check(lib, s, 200, block=block, flags=flags)
+    assert r.info["block_used"] == block
+    a_ls = np.linalg.lstsq(s.X(), s.y.astype(np.float64), rcond=None)[0]
+    assert rel(r.a.cpu().numpy(), a_ls) < 1e-5
+    assert r.info["final_rel_resid"] == pytest.approx(oracle.final_rel_resid(s.Xt, s.y, s.m, ref.a), rel=1e-4)
+
+
+@pytest.mark.parametrize("m,n", [(1, 3), (5, 2), (1999, 37), (2001, 9), (4093, 21), (4096, 64)])
+def test_ragged_shapes(lib, m, n):
+    """Rows not a multiple of the 16-byte chunk, columns not a multiple of the
+    block, NaN padding rows."""
+    say("ragged", m, n)
+    rng = np.random.default_rng(m * 1000 + n)
+    s = gen.make_system(rng, m, n, noise=0.01, pad=np.nan)
+    for flags in (0, lib.F_FORCE_GRID):
+        check(lib, s, 15, flags=flags)
+
+
+def test_tall_grid_multi_wg(lib):
+    """Several hundred thousand rows: a persistent grid of many workgroups."""
+    s = gen.tall_large(m=300_001, n=40, seed=7, pad=np.nan)
+    say("tall grid 300001x40")
+    for block in (1, 8):
+        r, _ = check(lib, s, 4, block=block)
+        assert r.info["team_wgs"] > 1
+
+
+def test_tall_large_full_size_two_sweeps(lib):
+    """The 1,000,000 x 256 bandwidth workload, in the launch configuration the
+    benchmark uses, against the oracle after 2 sweeps."""
+    s = gen.tall_large()
+    say("tall_large full size")
+    r, ref = check(lib, s, 2)
+    say("info", r.info)
+
+
+def test_wide_workgroup(lib):
+    s = gen.wide(m=2000, n=20000, seed=11)
+    say("wide 2000x20000")
+    r, ref = check(lib, s, 3)
+    # consistent system: residual falls far below ||y||
+    assert r.hist[-1] < 1e-2 * r.hist[0]
+
+
+# ------------------------------------------------------------ semantics
+
+def test_zero_columns_skipped(lib):
+    rng = np.random.default_rng(3)
+    s = gen.make_system(rng, 700, 12, noise=0.01)
+    s.Xt[[2, 7], :] = 0.0
+    say("zero columns")
+    r, ref = check(lib, s, 30)
+    assert r.info["zero_cols"] == 2 and ref.zero_cols == 2
+    assert r.a.cpu().numpy()[2] == 0.0
+
+
+def test_warm_start_resume(lib):
+    """a0 = result of k sweeps, k more sweeps == 2k sweeps (to tolerance)."""
+    s = gen.tall_small()
+    say("warm start")
+    r4 = run(lib, s, 4)
+    r2 = run(lib, s, 2)
+    rr = run(lib, s, 2, a0=r2.a.cpu().numpy())
+    assert rel(rr.a.cpu().numpy(), r4.a.cpu().numpy()) < 1e-5
+    check(lib, s, 3, a0=np.random.default_rng(1).standard_normal(s.n).astype(np.float32))
+
+
+def test_hist_monotone(lib):
+    s = gen.tall_large(m=200_000, n=64, seed=3)
+    say("monotone")
+    r = run(lib, s, 12)
+    h = np.asarray(r.hist)
+    assert np.all(h[1:] <= h[:-1] + 1e-6 * h[0])
+
+
+def test_deterministic(lib):
+    s = gen.tall_large(m=200_000, n=64, seed=3)
+    say("deterministic")
+    r1 = run(lib, s, 5)
+    r2 = run(lib, s, 5)
+    assert np.array_equal(r1.a.cpu().numpy(), r2.a.cpu().numpy())
+    assert np.array_equal(r1.hist, r2.hist)
+
+
+def test_stop_rel_change_matches_oracle(lib):
+    s = gen.tall_small()
+    say("stop rel change")
+    r = run(lib, s, 200, stop=lib.STOP_REL_CHANGE, tol=1e-3)
+    ref = oracle.solve(s.Xt, s.y, s.m, max_sweeps=200, tol=1e-3, stop=oracle.STOP_REL_CHANGE)
+    assert r.info["converged"] == 1 and r.info["sweeps_done"] == ref.sweeps
+    assert rel(r.a.cpu().numpy(), ref.a) < TOL_A
+
+
+def test_stop_rel_resid_with_column_checks(lib):
+    s = gen.square_well_conditioned(64, seed=8)
+    s32 = gen.System(s.Xt.astype(np.float32), s.y.astype(np.float32), 64, 64)
+    say("stop rel resid")
+    r = run(lib, s32, 500, stop=lib.STOP_REL_RESID, tol=1e-4, check_cols=8)
+    ref = oracle.solve(s32.Xt, s32.y, 64, max_sweeps=500, tol=1e-4, stop=oracle.STOP_REL_RESID, check_cols=8)
+    assert r.info["converged"] == 1
+    assert r.info["cols_done"] == ref.cols
+    assert rel(r.a.cpu().numpy(), ref.a) < TOL_A
+
+
+def test_nonfinite_rejected(lib):
+    s = gen.tall_small(m=300, n=10)
+    s.Xt[3, 17] = np.inf
+    say("nonfinite")
+    with pytest.raises(lib.HPSCDError) as ei:
+        run(lib, s, 3)
+    assert ei.value.status == lib.ENONFINITE
+    s = gen.tall_small(m=300, n=10)
+    s.y[5] = np.nan
+    with pytest.raises(lib.HPSCDError) as ei:
+        run(lib, s, 3)
+    assert ei.value.status == lib.ENONFINITE
+    # the context stays usable
+    check(lib, gen.tall_small(m=300, n=10), 3)
+
+
+def test_zero_sweeps(lib):
+    s = gen.tall_small(m=300, n=10)
+    r = run(lib, s, 0)
+    assert np.all(r.a.cpu().numpy() == 0) and len(r.hist) == 1
+    assert r.hist[0] == pytest.approx(np.linalg.norm(s.y.astype(np.float64)), rel=1e-6)
+
+
+def test_residual_f64(lib):
+    s = gen.tall_small()
+    a = np.random.default_rng(0).standard_normal(s.n).astype(np.float32)
+    nrm, e = lib.residual_f64(dev(s.Xt), dev(s.y), dev(a), want_e=True)
+    ref = oracle.residual(s.Xt, s.y, s.m, a.astype(np.float64))
+    assert nrm == pytest.approx(np.linalg.norm(ref), rel=1e-12)
+    np.testing.assert_allclose(e.cpu().numpy(), ref.astype(np.float32), rtol=1e-6, atol=1e-6)
