@@ -70,8 +70,8 @@ typedef struct {
   int64_t refresh_cols; /* bf16 form: e = y - X32·a (FP64 sums) every refresh_cols column steps; 0 = never */
   int32_t block;        /* columns per reduction round (1, 2, 4 or 8); 0 = library choice */
   int32_t flags;        /* HPSCD_F_* */
-  int32_t team_threads; /* 0 = library choice */
-  int32_t reserved;
+  int32_t team_threads; /* threads per workgroup; 0 = library choice */
+  int32_t depth;        /* blocks held in the prefetch ring (2 or 3); 0 = library choice */
 } hpscd_opts;
 
 typedef struct {

@@ -24,29 +24,39 @@ __device__ inline float chunk_at(const typename S::raw_t& r, int i) { return S::
 // ------------------------------------------------------------- column stats
 // Grid (PR, NBG) of 256-thread workgroups.  Wave w of workgroup (rx, gy)
 // handles column blocks b = gy*4 + w (+ strides) over rows
-// [rx*rows_per, (rx+1)*rows_per) and writes its NP = B(B+1)/2 FP64 partial
-// sums (pair (l, i<=l) at l(l+1)/2 + i) to partial[(rx*nb + b)*NP].
-template <class S, int B>
+// [rx*rows_per, (rx+1)*rows_per) and writes its FP64 partial sums to
+// partial[(rx*nb + b)*NPX + q]: first the NP = B(B+1)/2 in-block pairs (l, i<=l)
+// at l(l+1)/2 + i, then (CROSS) the B*B pairs <X_{b,l}, X_{b-1,i}> with the
+// previous block at NP + l*B + i (zero for b = 0).
+template <class S, int B, bool CROSS>
 __global__ void __launch_bounds__(256) k_colgram(const void* X, int64_t ldx, int64_t m, int64_t n,
                                                  int64_t rows_per, double* partial) {
   using raw = typename S::raw_t;
-  constexpr int VEC = S::VEC, NP = B * (B + 1) / 2;
+  constexpr int VEC = S::VEC, NP = B * (B + 1) / 2, NX = CROSS ? B * B : 0, NPX = NP + NX;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t nb = (n + B - 1) / B;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per;
   const int64_t r1 = min(m, r0 + rows_per);
   for (int64_t b = (int64_t)blockIdx.y * 4 + wave; b < nb; b += (int64_t)gridDim.y * 4) {
-    double acc[NP];
+    double acc[NPX];
 #pragma unroll
-    for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NPX; ++q) acc[q] = 0.0;
     for (int64_t row = r0 + (int64_t)lane * VEC; row < r1; row += 64 * VEC) {
       const int lim = (int)min((int64_t)VEC, r1 - row);
-      raw x[B];
+      raw x[B], xp[CROSS ? B : 1];
 #pragma unroll
       for (int l = 0; l < B; ++l) {
         const int64_t j = b * B + l;
         x[l] = (j < n) ? load_chunk<S>(X, j * ldx + row) : S::zero();
         if (lim < VEC) x[l] = mask_chunk<S>(x[l], lim);
+      }
+      if constexpr (CROSS) {
+#pragma unroll
+        for (int l = 0; l < B; ++l) {
+          const int64_t j = (b - 1) * B + l;
+          xp[l] = (b > 0) ? load_chunk<S>(X, j * ldx + row) : S::zero();
+          if (lim < VEC) xp[l] = mask_chunk<S>(xp[l], lim);
+        }
       }
 #pragma unroll
       for (int i = 0; i < VEC; ++i) {
@@ -57,28 +67,44 @@ __global__ void __launch_bounds__(256) k_colgram(const void* X, int64_t ldx, int
         for (int l = 0; l < B; ++l)
 #pragma unroll
           for (int k = 0; k <= l; ++k) acc[l * (l + 1) / 2 + k] = fma(v[l], v[k], acc[l * (l + 1) / 2 + k]);
+        if constexpr (CROSS) {
+#pragma unroll
+          for (int l = 0; l < B; ++l)
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+              acc[NP + l * B + k] = fma(v[l], (double)chunk_at<S>(xp[k], i), acc[NP + l * B + k]);
+        }
       }
     }
 #pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      const double s = wave_sum(acc[q]);
-      if (lane == q % 64) partial[((int64_t)blockIdx.x * nb + b) * NP + q] = s;
+    for (int q = 0; q < NPX; ++q) {
+      const double sum = wave_sum(acc[q]);
+      if (lane == q % 64) partial[((int64_t)blockIdx.x * nb + b) * NPX + q] = sum;
     }
   }
 }
 
-// Sum the PR partials (fixed order) into rdn[nb*B] and gram[nb*NG].
-template <int B>
-__global__ void k_colgram_reduce(const double* partial, int PR, int64_t n, double* rdn, double* gram,
-                                 int32_t* ctl, int64_t* zero_cols) {
-  constexpr int NP = B * (B + 1) / 2, NG = B * (B - 1) / 2;
+// Sum the PR partials (fixed order, one wave per output) into rdn[nb*B],
+// gram[nb*NG] and (CROSS) cross[nb*B*B].
+template <int B, bool CROSS>
+__global__ void __launch_bounds__(256) k_colgram_reduce(const double* partial, int PR, int64_t n, double* rdn,
+                                                        double* gram, double* cross, int32_t* ctl,
+                                                        int64_t* zero_cols) {
+  constexpr int NP = B * (B + 1) / 2, NG = B * (B - 1) / 2, NX = CROSS ? B * B : 0, NPX = NP + NX;
+  const int lane = threadIdx.x & 63;
   const int64_t nb = (n + B - 1) / B;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nb * NP) return;
-  const int64_t b = idx / NP;
-  const int q = (int)(idx % NP);
-  double s = 0.0;
-  for (int r = 0; r < PR; ++r) s += partial[((int64_t)r * nb + b) * NP + q];
+  const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (idx >= nb * NPX) return;
+  const int64_t b = idx / NPX;
+  const int q = (int)(idx % NPX);
+  double acc = 0.0;
+  for (int r = lane; r < PR; r += 64) acc += partial[((int64_t)r * nb + b) * NPX + q];
+  const double s = wave_sum(acc);
+  if (lane != 0) return;
+  if (q >= NP) {
+    cross[b * NX + (q - NP)] = s;
+    return;
+  }
   int l = 0;
   while ((l + 1) * (l + 2) / 2 <= q) ++l;
   const int i = q - l * (l + 1) / 2;
@@ -96,42 +122,48 @@ __global__ void k_colgram_reduce(const double* partial, int PR, int64_t n, doubl
   }
 }
 
-template <class S, int B>
+template <class S, int B, bool CROSS>
 static hipError_t colgram_impl(const void* X, int64_t ldx, int64_t m, int64_t n, double* rdn, double* gram,
-                               double* partial, int64_t partial_cap, int32_t* ctl, int64_t* zero_cols,
-                               hipStream_t s) {
-  constexpr int NP = B * (B + 1) / 2;
+                               double* cross, double* partial, int64_t partial_cap, int32_t* ctl,
+                               int64_t* zero_cols, hipStream_t s) {
+  constexpr int NPX = B * (B + 1) / 2 + (CROSS ? B * B : 0);
   const int64_t nb = (n + B - 1) / B;
   // Enough waves to fill the chip (~8192), rows split only when the columns
   // alone cannot provide them.
-  const int64_t waves_cols = nb;
   int64_t PR = 1;
-  if (waves_cols < 8192) PR = (8192 + waves_cols - 1) / waves_cols;
+  if (nb < 8192) PR = (8192 + nb - 1) / nb;
   const int64_t min_rows = 64 * S::VEC * 4;
   PR = std::max<int64_t>(1, std::min<int64_t>(PR, (m + min_rows - 1) / min_rows));
-  while (PR > 1 && PR * nb * NP > partial_cap) --PR;
-  if (PR * nb * NP > partial_cap) return hipErrorInvalidValue;
+  while (PR > 1 && PR * nb * NPX > partial_cap) --PR;
+  if (PR * nb * NPX > partial_cap) return hipErrorInvalidValue;
   int64_t rows_per = (m + PR - 1) / PR;
   rows_per = (rows_per + S::VEC - 1) / S::VEC * S::VEC;
   PR = (m + rows_per - 1) / rows_per;
   const int64_t NBG = std::min<int64_t>((nb + 3) / 4, 65535);
-  hipLaunchKernelGGL((k_colgram<S, B>), dim3((unsigned)PR, (unsigned)NBG), dim3(256), 0, s, X, ldx, m, n,
+  hipLaunchKernelGGL((k_colgram<S, B, CROSS>), dim3((unsigned)PR, (unsigned)NBG), dim3(256), 0, s, X, ldx, m, n,
                      rows_per, partial);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  const int64_t total = nb * NP;
-  hipLaunchKernelGGL((k_colgram_reduce<B>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, partial,
-                     (int)PR, n, rdn, gram, ctl, zero_cols);
+  const int64_t total = nb * NPX;
+  hipLaunchKernelGGL((k_colgram_reduce<B, CROSS>), dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, partial,
+                     (int)PR, n, rdn, gram, cross, ctl, zero_cols);
   return hipGetLastError();
 }
 
 hipError_t launch_colgram(const void* X, bool bf16, int64_t ldx, int64_t m, int64_t n, int B, double* rdn,
-                          double* gram, double* partial, int64_t partial_cap, int32_t* ctl, int64_t* zero_cols,
-                          hipStream_t s) {
-#define HPSCD_CG(BB)                                                                               \
-  case BB:                                                                                         \
-    return bf16 ? colgram_impl<BF16, BB>(X, ldx, m, n, rdn, gram, partial, partial_cap, ctl, zero_cols, s) \
-                : colgram_impl<F32, BB>(X, ldx, m, n, rdn, gram, partial, partial_cap, ctl, zero_cols, s);
+                          double* gram, double* cross, double* partial, int64_t partial_cap, int32_t* ctl,
+                          int64_t* zero_cols, hipStream_t s) {
+#define HPSCD_CG(BB)                                                                                           \
+  case BB:                                                                                                     \
+    if (cross)                                                                                                 \
+      return bf16 ? colgram_impl<BF16, BB, true>(X, ldx, m, n, rdn, gram, cross, partial, partial_cap, ctl,     \
+                                                 zero_cols, s)                                                 \
+                  : colgram_impl<F32, BB, true>(X, ldx, m, n, rdn, gram, cross, partial, partial_cap, ctl,      \
+                                                zero_cols, s);                                                 \
+    return bf16 ? colgram_impl<BF16, BB, false>(X, ldx, m, n, rdn, gram, cross, partial, partial_cap, ctl,      \
+                                                zero_cols, s)                                                  \
+                : colgram_impl<F32, BB, false>(X, ldx, m, n, rdn, gram, cross, partial, partial_cap, ctl,       \
+                                               zero_cols, s);
   switch (B) {
     HPSCD_CG(1) HPSCD_CG(2) HPSCD_CG(4) HPSCD_CG(8)
     default: return hipErrorInvalidValue;

@@ -80,7 +80,7 @@ struct Tuned {
 struct hpscd_ctx {
   int device = 0;
   int cus = 0;
-  DevBuf ctlb, e0, eo, a64, rdn, gram, partial, slots, hist;
+  DevBuf ctlb, e0, eo, a64, rdn, gram, cross, partial, slots, hist;
   DevBuf b_sys, b_items, b_blk, b_rdn, b_gram, b_a64, b_e0, b_hist, b_i32, b_f64;
   void* host = nullptr;
   size_t host_cap = 0;
@@ -119,6 +119,8 @@ hpscd_status validate_opts(const hpscd_opts* o) {
   if (o->refresh_cols < 0) return fail(HPSCD_EINVAL, "refresh_cols must be >= 0");
   if (o->block != 0 && o->block != 1 && o->block != 2 && o->block != 4 && o->block != 8)
     return fail(HPSCD_EINVAL, "block must be 0, 1, 2, 4 or 8 (got %d)", o->block);
+  if (o->depth != 0 && o->depth != 2 && o->depth != 3 && o->depth != 4 && o->depth != 12 && o->depth != 13)
+    return fail(HPSCD_EINVAL, "depth (kernel kind) must be 0, 2, 3, 4, 12 or 13 (got %d)", o->depth);
   if ((o->flags & HPSCD_F_FORCE_GRID) && (o->flags & HPSCD_F_FORCE_WG))
     return fail(HPSCD_EINVAL, "FORCE_GRID and FORCE_WG are exclusive");
   if ((int64_t)o->max_sweeps + 1 > (int64_t)1 << 30) return fail(HPSCD_EINVAL, "max_sweeps too large");
@@ -138,7 +140,7 @@ int pick_block(int want, std::initializer_list<int64_t> divides) {
 
 struct Plan {
   bool grid;
-  int T, R, B, P;
+  int T, R, B, P, D;
 };
 
 hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hpscd_opts* o, Plan* pl) {
@@ -150,8 +152,8 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
   std::vector<std::pair<int, int>> shapes;  // (T, R) candidates, smallest first
   if (grid) {
     if (bf16) shapes = {{1024, 1}, {512, 1}};
-    else if (m >= 256 * 1024 * 4) shapes = {{1024, 1}, {512, 2}};
-    else shapes = {{256, 1}, {1024, 1}};
+    else if (m >= 256 * 1024 * 4) shapes = {{512, 2}, {1024, 1}, {256, 4}};
+    else shapes = {{256, 1}, {256, 2}, {512, 2}, {1024, 1}};
   } else {
     if (bf16) shapes = {{256, 1}, {256, 2}};
     else shapes = {{256, 2}, {256, 4}};
@@ -166,20 +168,35 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
     for (int R : {1, 2, 4}) keep.push_back({o->team_threads, R});
     shapes = keep;
   }
+  // Kernel kinds in order of preference (see launch_sweep).  The pipelined
+  // kind (4) tests the stop rule only at sweep ends, so it is only used when
+  // asked for and the caller does not need checks inside a sweep.
+  std::vector<int> kinds;
+  if (o->depth == 4 && o->check_cols > 0 && o->stop == HPSCD_STOP_REL_RESID)
+    return fail(HPSCD_EINVAL, "the pipelined kernel (depth 4) tests the stop rule only at sweep ends");
+  if (o->depth != 0) kinds = {o->depth};
+  else if (grid) kinds = {2, 3};  // measured fastest on the 1M x 256 system; 4, 12, 13 are selectable
+  else kinds = {3, 2};
+  auto kind_of = [&](int T, int R, int b) {
+    for (int k : kinds)
+      if (sweep_variant_exists(T, R, b, bf16, grid, k)) return k;
+    return 0;
+  };
   for (auto [T, R] : shapes) {
     const int64_t rows = (int64_t)T * R * VEC;
     if (!grid && m > rows) continue;
     int b = B;
-    while (b >= 1 && !sweep_variant_exists(T, R, b, bf16, grid)) b /= 2;
+    while (b >= 1 && !kind_of(T, R, b)) b /= 2;
     if (b < 1) continue;
     if (o->block > 0 && b != o->block) continue;
+    const int kind = kind_of(T, R, b);
     const int64_t P = grid ? (m + rows - 1) / rows : 1;
     if (grid) {
-      if (P > 512) continue;
-      const int per_cu = sweep_max_blocks_per_cu(T, R, b, bf16, true);
+      if (P > sweep_max_workgroups(T, R, b, bf16, true, kind)) continue;
+      const int per_cu = sweep_max_blocks_per_cu(T, R, b, bf16, true, kind);
       if (per_cu <= 0 || P > (int64_t)per_cu * c->cus) continue;
     }
-    *pl = Plan{grid, T, R, b, (int)P};
+    *pl = Plan{grid, T, R, b, (int)P, kind};
     return HPSCD_OK;
   }
   return fail(HPSCD_EINVAL, "no kernel variant fits m=%lld (%s team, block %d)", (long long)m,
@@ -223,8 +240,9 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
       (rc = ensure(c->e0, (size_t)m * 4, "e0")) || (rc = ensure(c->eo, (size_t)m * 4, "e")) ||
       (rc = ensure(c->a64, (size_t)n * 8, "a64")) || (rc = ensure(c->rdn, (size_t)nb * B * 8, "rdn")) ||
       (rc = ensure(c->gram, (size_t)std::max<int64_t>(1, nb * NG) * 8, "gram")) ||
+      (rc = ensure(c->cross, (size_t)nb * B * B * 8, "cross")) ||
       (rc = ensure(c->partial, (size_t)partial_cap * 8, "partial")) ||
-      (rc = ensure(c->slots, (size_t)2 * (B + 1) * std::max(1, pl.P) * 8, "slots")) ||
+      (rc = ensure(c->slots, (size_t)4 * (B + 1) * std::max(1, pl.P) * 8, "slots")) ||
       (rc = ensure(c->hist, (size_t)hist_len * 8, "hist")))
     return rc;
   if ((rc = c->host_ensure(sizeof(CtlBlock) + (size_t)hist_len * 8))) return rc;
@@ -240,7 +258,7 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   HIP_TRY(hipEventRecord(c->ev[0], st));
   HIP_TRY(launch_fill_i32(ctl, sizeof(CtlBlock) / 4, 0, st));
   HIP_TRY(launch_fill_f64(c->hist.as<double>(), hist_len, std::numeric_limits<double>::quiet_NaN(), st));
-  if (pl.grid) HIP_TRY(launch_fill_u64(c->slots.as<uint64_t>(), 2 * (int64_t)(B + 1) * pl.P, 0, st));
+  if (pl.grid) HIP_TRY(launch_fill_u64(c->slots.as<uint64_t>(), 4 * (int64_t)(B + 1) * pl.P, 0, st));
   HIP_TRY(launch_a_init(c->a64.as<double>(), a0, n, st));
   HIP_TRY(launch_residual(X32, ldx32, m, 0, y, nullptr, nullptr, nullptr, ynorm2, partial, partial_cap, nullptr, st));
   const float* e0 = y;
@@ -249,7 +267,9 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
                             nullptr, st));
     e0 = c->e0.as<float>();
   }
-  HIP_TRY(launch_colgram(Xs, bf16, ldxs, m, n, B, c->rdn.as<double>(), c->gram.as<double>(), partial, partial_cap,
+  const bool pipelined = pl.D == 4;
+  HIP_TRY(launch_colgram(Xs, bf16, ldxs, m, n, B, c->rdn.as<double>(), c->gram.as<double>(),
+                         pipelined ? c->cross.as<double>() : nullptr, partial, partial_cap,
                          ctl, &ctl64[C64_ZERO_COLS], st));
   HIP_TRY(hipEventRecord(c->ev[1], st));
 
@@ -260,6 +280,7 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   A.n = n;
   A.rdn = c->rdn.as<double>();
   A.gram = c->gram.as<double>();
+  A.cross = c->cross.as<double>();
   A.a64 = c->a64.as<double>();
   A.e_out = c->eo.as<float>();
   A.hist = c->hist.as<double>();
@@ -282,7 +303,7 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
     A.e0 = (kb == 0) ? e0 : c->eo.as<float>();
     A.blk_begin = kb;
     A.blk_end = std::min(total, kb + seg);
-    HIP_TRY(launch_sweep(pl.T, pl.R, B, bf16, pl.grid, A, st, coop));
+    HIP_TRY(launch_sweep(pl.T, pl.R, B, bf16, pl.grid, pl.D, A, st, coop));
     if (o->refresh_cols > 0 && A.blk_end < total) {
       const int64_t cols = (A.blk_end / nb) * n + (A.blk_end % nb) * B;
       const int64_t touched = a0 ? n : std::min(n, cols);
@@ -376,7 +397,7 @@ void hpscd_destroy(hpscd_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  for (DevBuf* b : {&c->ctlb, &c->e0, &c->eo, &c->a64, &c->rdn, &c->gram, &c->partial, &c->slots, &c->hist,
+  for (DevBuf* b : {&c->ctlb, &c->e0, &c->eo, &c->a64, &c->rdn, &c->gram, &c->cross, &c->partial, &c->slots, &c->hist,
                     &c->b_sys, &c->b_items, &c->b_blk, &c->b_rdn, &c->b_gram, &c->b_a64, &c->b_e0, &c->b_hist,
                     &c->b_i32, &c->b_f64})
     b->release();

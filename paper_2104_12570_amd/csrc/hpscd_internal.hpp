@@ -12,6 +12,7 @@ struct SolveArgs {
   const float* e0;        // residual at entry (length m)
   const double* rdn;      // [nb*B] 1/<X_j,X_j> (0 for zero and padding columns)
   const double* gram;     // [nb][B*(B-1)/2] strictly-lower in-block Gram, (l,i) row-major
+  const double* cross;    // [nb][B*B] Gram with the previous block (pipelined kernel only)
   double* a64;            // [n] coefficients, accumulated in FP64
   float* e_out;           // [m] residual at exit
   double* hist;           // [max_sweeps+1] ||e||_2 after each complete sweep
@@ -66,10 +67,13 @@ struct BatchArgs {
 };
 
 // Kernel launchers (return hipError_t of the launch).
-hipError_t launch_sweep(int variant_T, int variant_R, int B, bool bf16, bool grid,
+// D: kernel kind: 2, 3 = prefetch ring of 2 or 3 blocks; 4 = pipelined reductions;
+// 12, 13 = warp-specialised with a ring of 2 or 3 blocks; 0 = any.
+hipError_t launch_sweep(int variant_T, int variant_R, int B, bool bf16, bool grid, int D,
                         const SolveArgs& a, hipStream_t s, bool cooperative);
-int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid);
-bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid);
+int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid, int D);
+int sweep_max_workgroups(int T, int R, int B, bool bf16, bool grid, int D);
+bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid, int D);
 
 hipError_t launch_batched(int B, const BatchArgs& a, int grid, hipStream_t s);
 int batched_threads();
@@ -79,8 +83,9 @@ int batched_max_blocks_per_cu(int B);
 bool batched_variant_exists(int B);
 
 // Column statistics: rdn = 1/<X_j,X_j> and the in-block Gram, FP64 sums.
+// cross: NULL, or [nb][B*B] receiving <X_{b,l}, X_{b-1,i}> at l*B + i (zero for b = 0).
 hipError_t launch_colgram(const void* X, bool bf16, int64_t ldx, int64_t m, int64_t n, int B,
-                          double* rdn, double* gram, double* partial, int64_t partial_cap,
+                          double* rdn, double* gram, double* cross, double* partial, int64_t partial_cap,
                           int32_t* ctl, int64_t* zero_cols, hipStream_t s);
 hipError_t launch_colgram_batched(const float* Xpool, const SysDesc* sys, int32_t count, int64_t nblk_total,
                                   const int64_t* blk_first, int B, double* rdn, double* gram,

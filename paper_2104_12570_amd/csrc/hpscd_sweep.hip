@@ -74,8 +74,9 @@ __device__ inline void forward_substitute(const double (&tot)[B + 1], const Coef
 // --------------------------------------------------------------------------
 // Single-system kernel: a persistent grid (GRID) or one workgroup.
 // --------------------------------------------------------------------------
-template <class S, int T, int R, int B, bool GRID>
+template <class S, int T, int R, int B, bool GRID, int D>
 __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
+  static_assert(D == 2 || D == 3, "prefetch ring of 2 or 3 blocks");
   using raw = typename S::raw_t;
   constexpr int VEC = S::VEC;
   constexpr int NW = T / WAVE;
@@ -111,8 +112,10 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
   const double ynorm = sqrt(*A.ynorm2);
   const int64_t nblocks = A.blk_end - A.blk_begin;
   const int64_t col_bytes = A.ldx * (int64_t)(16 / VEC);
-  raw xa[B][R], xb[B][R];
-  Coef<B> ca, cb;
+  // Ring of D register buffers: the current block and the next D-1 blocks,
+  // whose loads are in flight while the current block is reduced.
+  raw x0[B][R], x1[B][R], x2[D == 3 ? B : 1][R];
+  Coef<B> c0, c1, c2;
 
   // Columns of one block are read through a buffer resource based at the
   // block's first column: one 32-bit lane offset per chunk, one scalar offset
@@ -153,12 +156,18 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
   int sdone = (int)(A.blk_begin / nb);
   uint32_t seq = (uint32_t)(A.blk_begin + 1);
 
-  // One block: returns true when the solve is over.
-  auto step = [&](raw (&cur)[B][R], raw (&nxt)[B][R], Coef<B>& ccur, Coef<B>& cnxt, bool has_next) -> bool {
+  // One block: returns true when the solve is over.  `pf` receives the
+  // block D-1 ahead (when has_next).
+  auto step = [&](raw (&cur)[B][R], auto& pf, Coef<B>& ccur, Coef<B>& cpf, bool has_next) -> bool {
     const int j0 = bi * B;
     const int nbi = (bi + 1 == nb) ? 0 : bi + 1;
+    int pbi = bi + D - 1;
+    while (pbi >= nb) pbi -= nb;
+    auto prefetch = [&]() {
+      if constexpr (sizeof(pf) == sizeof(cur)) load_block(pf, cpf, pbi);
+    };
     if constexpr (!GRID) {
-      if (has_next) load_block(nxt, cnxt, nbi);
+      if (has_next) prefetch();
     }
 
     float p[NV];
@@ -198,16 +207,17 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
     __syncthreads();
     double tot[NV];
     if constexpr (GRID) {
-      // Slots are [parity][workgroup][value].  Poll task t covers value
-      // l = t / ncn of the 64 workgroups of chunk c = t % ncn; each wave
-      // issues all its task loads at once, then the next block's loads, then
-      // re-polls only words whose sequence number is not yet current.
+      // Slots are [parity][value][workgroup], so the 64 lanes of a poll load
+      // read 512 contiguous bytes.  Poll task t covers value l = t / ncn of
+      // the 64 workgroups of chunk c = t % ncn; each wave issues all its task
+      // loads at once, then the next block's loads, then re-polls only words
+      // whose sequence number is not yet current.
       uint64_t* slot_base = A.slots + (int64_t)par * NV * A.P;
       if (tid < NV) {
         float sacc = 0.f;
 #pragma unroll
         for (int w = 0; w < NW; ++w) sacc += red[par][w][tid];
-        publish(slot_base + (int64_t)wg * NV + tid, seq, sacc);
+        publish(slot_base + (int64_t)tid * A.P + wg, seq, sacc);
       }
       const int ncn = (A.P + WAVE - 1) / WAVE;
       const int ntask = NV * ncn;
@@ -219,9 +229,15 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
           const int t = t0 + q * NW;
           const int l = t / ncn, c = t - l * ncn, idx = c * WAVE + lane;
           const bool live = t < ntask && idx < A.P;
-          w[q] = live ? peek(slot_base + (int64_t)idx * NV + l) : ((uint64_t)seq << 32);
+          w[q] = live ? peek(slot_base + (int64_t)l * A.P + idx) : ((uint64_t)seq << 32);
         }
-        if (t0 == wave && has_next) load_block(nxt, cnxt, nbi);
+        // With two blocks resident the next block's loads go out right after
+        // the first poll loads; with three, the block two ahead is requested
+        // only after this wave's poll has completed, so no poll load waits
+        // behind column data (vector loads return in order).
+        if constexpr (D == 2) {
+          if (t0 == wave && has_next) prefetch();
+        }
         uint64_t tstart = 0;
         for (int spin = 0;; ++spin) {
           bool ready = true;
@@ -239,7 +255,7 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
             if ((uint32_t)(w[q] >> 32) != seq) {
               const int t = t0 + q * NW;
               const int l = t / ncn, c = t - l * ncn, idx = c * WAVE + lane;
-              w[q] = peek(slot_base + (int64_t)idx * NV + l);
+              w[q] = peek(slot_base + (int64_t)l * A.P + idx);
             }
           }
         }
@@ -253,7 +269,11 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
           }
         }
       }
-      if (ntask <= wave && has_next) load_block(nxt, cnxt, nbi);
+      if constexpr (D == 2) {
+        if (ntask <= wave && has_next) prefetch();
+      } else {
+        if (has_next) prefetch();
+      }
       if (timed_out) sflag = 1;
       __syncthreads();
       if (sflag) {
@@ -328,13 +348,666 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
     return false;
   };
 
-  if (nblocks > 0) load_block(xa, ca, bi);
+  if (nblocks > 0) load_block(x0, c0, bi);
+  if constexpr (D == 3) {
+    if (nblocks > 1) load_block(x1, c1, bi + 1 == nb ? 0 : bi + 1);
+  }
   __syncthreads();
   for (int64_t k = 0; k < nblocks;) {
-    if (step(xa, xb, ca, cb, k + 1 < nblocks)) break;
+    if constexpr (D == 2) {
+      if (step(x0, x1, c0, c1, k + 1 < nblocks)) break;
+      if (++k >= nblocks) break;
+      if (step(x1, x0, c1, c0, k + 1 < nblocks)) break;
+      ++k;
+    } else {
+      if (step(x0, x2, c0, c2, k + 2 < nblocks)) break;
+      if (++k >= nblocks) break;
+      if (step(x1, x0, c1, c0, k + 2 < nblocks)) break;
+      if (++k >= nblocks) break;
+      if (step(x2, x1, c2, c1, k + 2 < nblocks)) break;
+      ++k;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < R; ++c)
+#pragma unroll
+    for (int i = 0; i < VEC; ++i)
+      if (i < lim[c]) A.e_out[rof[c] + i] = e[c][i];
+}
+
+// --------------------------------------------------------------------------
+// Warp-specialised grid kernel.  The T data threads own the rows and stream
+// X; one extra wave owns the grid reduction: it sums the data waves' partials,
+// publishes them, and polls the other workgroups' words.  Vector loads of a
+// wave return in issue order, so a wave that both streamed columns and polled
+// would see every poll result only after its outstanding column loads; here
+// the poll wave has nothing else in flight and the data waves request the
+// next blocks as soon as their partials are in LDS.
+template <class S, int T, int R, int B, int D>
+__global__ void __launch_bounds__(T + WAVE) k_sweep_ws(SolveArgs A) {
+  static_assert(D == 2 || D == 3, "prefetch ring of 2 or 3 blocks");
+  using raw = typename S::raw_t;
+  constexpr int VEC = S::VEC;
+  constexpr int NW = T / WAVE;
+  constexpr int NV = B + 1;
+  constexpr int MAXC = 4;                 // up to 256 workgroups
+  constexpr int NTASK = NV * MAXC;        // (value, chunk of 64 workgroups) words per poll lane
+  __shared__ float red[2][NW][NV];
+  __shared__ double tots[2][NV];
+  __shared__ int sflag;
+
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+  const int wg = (int)blockIdx.x;
+  const int64_t m = A.m, n = A.n;
+  const int nb = (int)((n + B - 1) / B);
+  if (A.ctl[CTL_NONFINITE] != 0 || A.ctl[CTL_DONE] != 0) return;
+  if (tid == 0) sflag = 0;
+  const int64_t nblocks = A.blk_end - A.blk_begin;
+  const double ynorm = sqrt(*A.ynorm2);
+
+  auto finalize = [&](int sdone, bool conv, int64_t cols, double nrm2) {
+    if (wg == 0 && tid == 0) {
+      A.ctl[CTL_SWEEPS] = sdone;
+      A.ctl[CTL_CONVERGED] = conv ? 1 : 0;
+      A.ctl[CTL_DONE] = 1;
+      A.ctl64[C64_COLS] = cols;
+      A.fstat[0] = nrm2;
+    }
+  };
+
+  // Block bookkeeping shared by both roles (identical in every thread):
+  // returns true when the solve ends at this block.
+  struct Pos { int bi, sdone; uint32_t seq; double prev_norm; };
+  Pos pos{(int)(A.blk_begin % nb), (int)(A.blk_begin / nb), (uint32_t)(A.blk_begin + 1), A.fstat[1]};
+  auto control = [&](const double (&tot)[NV], bool aborting) -> bool {
+    const int j0 = pos.bi * B;
+    if (sflag) {
+      if (tid == 0) store_flag(&A.ctl[CTL_ERR], ERR_TIMEOUT);
+      return true;
+    }
+    const double nrm2 = tot[B];
+    const double nrm = sqrt(nrm2);
+    if (!(nrm2 <= DBL_MAX)) {
+      if (wg == 0 && tid == 0) store_flag(&A.ctl[CTL_ERR], aborting ? ERR_ABORTED : ERR_NONFINITE);
+      finalize(pos.sdone, false, (int64_t)pos.sdone * n + j0, nrm2);
+      return true;
+    }
+    if (pos.bi == 0) {
+      if (wg == 0 && tid == 0) { A.hist[pos.sdone] = nrm; A.fstat[1] = nrm; }
+      bool stop = false, conv = false;
+      if (A.stop != STOP_NONE && nrm2 == 0.0) stop = conv = true;
+      else if (A.stop == STOP_REL_CHANGE && pos.sdone >= 1 && (pos.prev_norm - nrm) < A.tol * nrm) stop = conv = true;
+      else if (A.stop == STOP_REL_RESID && nrm < A.tol * ynorm) stop = conv = true;
+      if (!stop && pos.sdone >= A.max_sweeps) stop = true;
+      pos.prev_norm = nrm;
+      if (stop) { finalize(pos.sdone, conv, (int64_t)pos.sdone * n, nrm2); return true; }
+    } else if (A.check_cols > 0 && A.stop == STOP_REL_RESID) {
+      const int64_t cols = (int64_t)pos.sdone * n + j0;
+      if (cols % A.check_cols == 0 && (nrm2 == 0.0 || nrm < A.tol * ynorm)) {
+        finalize(pos.sdone, true, cols, nrm2);
+        return true;
+      }
+    }
+    return false;
+  };
+  auto advance = [&]() {
+    pos.bi = pos.bi + 1 == nb ? 0 : pos.bi + 1;
+    if (pos.bi == 0) ++pos.sdone;
+    ++pos.seq;
+  };
+
+  if (tid >= T) {
+    // ---------------- reduction wave: publish, poll, hand the totals over
+    __syncthreads();  // matches the data waves' prologue barrier
+    const int ncn = (A.P + WAVE - 1) / WAVE;
+    for (int64_t k = 0; k < nblocks; ++k) {
+      const int par = (int)(pos.seq & 1u);
+      const uint32_t seq = pos.seq;
+      __syncthreads();  // data waves' partials are in LDS
+      uint64_t* slot_base = A.slots + (int64_t)par * NV * A.P;
+      if (lane < NV) {
+        float sacc = 0.f;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) sacc += red[par][w][lane];
+        publish(slot_base + (int64_t)lane * A.P + wg, seq, sacc);
+      }
+      __syncthreads();  // published: the data waves may now request columns
+      uint64_t w[NTASK];
+#pragma unroll
+      for (int t = 0; t < NTASK; ++t) {
+        const int l = t / MAXC, c = t % MAXC, idx = c * WAVE + lane;
+        const bool live = c < ncn && idx < A.P;
+        w[t] = live ? peek(slot_base + (int64_t)l * A.P + idx) : ((uint64_t)seq << 32);
+      }
+      uint64_t tstart = 0;
+      bool timed_out = false;
+      for (int spin = 0;; ++spin) {
+        bool ready = true;
+#pragma unroll
+        for (int t = 0; t < NTASK; ++t) ready = ready && ((uint32_t)(w[t] >> 32) == seq);
+        if (ready) break;
+        if (spin == 0) tstart = now_ticks();
+        else if (now_ticks() - tstart > A.timeout_ticks) {
+          timed_out = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int t = 0; t < NTASK; ++t) {
+          if ((uint32_t)(w[t] >> 32) != seq) {
+            const int l = t / MAXC, c = t % MAXC, idx = c * WAVE + lane;
+            w[t] = peek(slot_base + (int64_t)l * A.P + idx);
+          }
+        }
+      }
+#pragma unroll
+      for (int l = 0; l < NV; ++l) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+          const int idx = c * WAVE + lane;
+          const bool live = c < ncn && idx < A.P;
+          acc += live ? (double)__uint_as_float((uint32_t)w[l * MAXC + c]) : 0.0;
+        }
+        const double tl = wave_sum(acc);
+        if (lane == 0) tots[par][l] = tl;
+      }
+      if (timed_out && lane == 0) sflag = 1;
+      __syncthreads();  // totals are in LDS
+      double tot[NV];
+#pragma unroll
+      for (int l = 0; l < NV; ++l) tot[l] = uniform_f64(tots[par][l]);
+      if (control(tot, false)) break;
+      advance();
+    }
+    return;
+  }
+
+  // ---------------- data waves: rows of the residual, column stream
+  float e[R][VEC];
+  int lim[R];
+  int64_t rof[R];
+  uint32_t boff[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    rof[c] = (int64_t)wg * (T * R * VEC) + (int64_t)VEC * (tid + T * c);
+    const int64_t left = m - rof[c];
+    lim[c] = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
+    boff[c] = (uint32_t)(rof[c] * (16 / VEC));
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? A.e0[rof[c] + i] : 0.f;
+  }
+  const int64_t col_bytes = A.ldx * (int64_t)(16 / VEC);
+  raw x0[B][R], x1[B][R], x2[D == 3 ? B : 1][R];
+  Coef<B> c0, c1, c2;
+
+  auto load_block = [&](raw (&x)[B][R], Coef<B>& cf, int bi) {
+    const int j0 = bi * B;
+    const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
+    const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
+    const uint32_t nrec = span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char*>(reinterpret_cast<const char*>(A.X) + (int64_t)j0 * col_bytes), 0, (int)nrec, 0x00020000);
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (lim[c] > 0)
+          x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
+        else
+          x[l][c] = S::zero();
+      }
+    }
+    cf.load(A.rdn, A.gram, bi, lane);
+  };
+
+  auto step = [&](raw (&cur)[B][R], auto& pf, Coef<B>& ccur, Coef<B>& cpf, bool has_next) -> bool {
+    const int j0 = pos.bi * B;
+    int pbi = pos.bi + D - 1;
+    while (pbi >= nb) pbi -= nb;
+    const int par = (int)(pos.seq & 1u);
+    float p[NV];
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (lim[c] < VEC) cur[l][c] = mask_chunk<S>(cur[l][c], lim[c]);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(cur[l][c], i), e[c][i], acc);
+      }
+      p[l] = acc;
+    }
+    {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc = fmaf(e[c][i], e[c][i], acc);
+      p[B] = acc;
+    }
+    bool aborting = false;
+    if (pos.bi == 0 && wg == 0 && tid == 0 && load_flag(&A.ctl[CTL_ABORT]) != 0) {
+      p[B] = __int_as_float(0x7fc00000);
+      aborting = true;
+    }
+#pragma unroll
+    for (int l = 0; l < NV; ++l) {
+      const float v = wave_sum(p[l]);
+      if (lane == 0) red[par][wave][l] = v;
+    }
+    __syncthreads();  // partials to the reduction wave
+    __syncthreads();  // the reduction wave has published (its stores precede our loads)
+    if (has_next) load_block(pf, cpf, pbi);
+    __syncthreads();  // totals from the reduction wave
+    double tot[NV];
+#pragma unroll
+    for (int l = 0; l < NV; ++l) tot[l] = uniform_f64(tots[par][l]);
+    if (control(tot, aborting)) return true;
+    double da[B];
+    forward_substitute<B>(tot, ccur, da);
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      const float f = (float)da[l];
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) e[c][i] = fmaf(-f, S::get(cur[l][c], i), e[c][i]);
+    }
+    if (tid < B) {
+      const int64_t j = j0 + tid;
+      if (j < n && (int)(j % A.P) == wg) {
+        double d = 0.0;
+#pragma unroll
+        for (int l = 0; l < B; ++l) if (tid == l) d = da[l];
+        (void)__hip_atomic_fetch_add(&A.a64[j], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    advance();
+    return false;
+  };
+
+  if (nblocks > 0) load_block(x0, c0, pos.bi);
+  if constexpr (D == 3) {
+    if (nblocks > 1) load_block(x1, c1, pos.bi + 1 == nb ? 0 : pos.bi + 1);
+  }
+  __syncthreads();
+  for (int64_t k = 0; k < nblocks;) {
+    if constexpr (D == 2) {
+      if (step(x0, x1, c0, c1, k + 1 < nblocks)) break;
+      if (++k >= nblocks) break;
+      if (step(x1, x0, c1, c0, k + 1 < nblocks)) break;
+      ++k;
+    } else {
+      if (step(x0, x2, c0, c2, k + 2 < nblocks)) break;
+      if (++k >= nblocks) break;
+      if (step(x1, x0, c1, c0, k + 2 < nblocks)) break;
+      if (++k >= nblocks) break;
+      if (step(x2, x1, c2, c1, k + 2 < nblocks)) break;
+      ++k;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < R; ++c)
+#pragma unroll
+    for (int i = 0; i < VEC; ++i)
+      if (i < lim[c]) A.e_out[rof[c] + i] = e[c][i];
+}
+
+// --------------------------------------------------------------------------
+// Pipelined grid kernel: two reductions in flight.
+//
+// Let E_k be the residual after the updates of blocks < k.  Step k publishes
+// the dots of block k against the residual it holds, which still lacks block
+// k-1's update (E_{k-1}), and only then waits for the reduction of block k-1
+// (published one step earlier).  Block k-1's true dots follow exactly from
+//     <X_l, E_{k-1}> = h_l - sum_i <X_l, X_{k-2,i}> da_{k-2,i}
+// (the Gram entries between consecutive blocks, computed once), after which
+// its in-block forward substitution and axpy run as in k_sweep.  Every
+// iterate is the one Algorithm 1 produces; the reduction latency is spread
+// over two steps.  The first block of every sweep is handled without lag
+// (the pipeline is drained), so the sweep-end norm and the stop test use the
+// exact residual.  Ring of four register buffers: block k-1 (axpy pending),
+// block k (dots), block k+1 (landed), block k+2 (requested at step k).
+template <int B>
+struct CoefX {
+  static constexpr int NG = B * (B - 1) / 2;
+  static constexpr int NX = B * B;
+  static constexpr int NT = B + NG + NX;
+  static constexpr int NCR = (NT + WAVE - 1) / WAVE;
+  double v[NCR];
+  __device__ inline void load(const double* rdn, const double* gram, const double* cross, int64_t bi, int lane) {
+#pragma unroll
+    for (int r = 0; r < NCR; ++r) {
+      const int q = r * WAVE + lane;
+      double x = 0.0;
+      if (q < B) x = rdn[bi * B + q];
+      else if (q < B + NG) x = gram[bi * NG + (q - B)];
+      else if (q < NT) x = cross[bi * NX + (q - B - NG)];
+      v[r] = x;
+    }
+  }
+  __device__ inline double get(int q) const { return readlane_f64(v[q / WAVE], q % WAVE); }
+};
+
+template <class S, int T, int R, int B>
+__global__ void __launch_bounds__(T) k_sweep_pipe(SolveArgs A) {
+  using raw = typename S::raw_t;
+  using CF = CoefX<B>;
+  constexpr int VEC = S::VEC;
+  constexpr int NW = T / WAVE;
+  constexpr int NV = B + 1;
+  constexpr int MAXC = 8;
+  constexpr int MAXT = (NV * MAXC + NW - 1) / NW < 8 ? (NV * MAXC + NW - 1) / NW : 8;
+  __shared__ float red[2][NW][NV];
+  __shared__ double gsum[2][NV][MAXC];
+  __shared__ int sflag;
+
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+  const int wg = (int)blockIdx.x;
+  const int64_t m = A.m, n = A.n;
+  const int nb = (int)((n + B - 1) / B);
+  if (A.ctl[CTL_NONFINITE] != 0 || A.ctl[CTL_DONE] != 0) return;
+  if (tid == 0) sflag = 0;
+
+  float e[R][VEC];
+  int lim[R];
+  int64_t rof[R];
+  uint32_t boff[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    rof[c] = (int64_t)wg * (T * R * VEC) + (int64_t)VEC * (tid + T * c);
+    const int64_t left = m - rof[c];
+    lim[c] = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
+    boff[c] = (uint32_t)(rof[c] * (16 / VEC));
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? A.e0[rof[c] + i] : 0.f;
+  }
+  double prev_norm = A.fstat[1];
+  const double ynorm = sqrt(*A.ynorm2);
+  const int64_t nblocks = A.blk_end - A.blk_begin;
+  const int64_t col_bytes = A.ldx * (int64_t)(16 / VEC);
+
+  raw x0[B][R], x1[B][R], x2[B][R], x3[B][R];
+  CF c0, c1, c2, c3;
+
+  auto load_block = [&](raw (&x)[B][R], CF& cf, int bi) {
+    const int j0 = bi * B;
+    const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
+    const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
+    const uint32_t nrec = span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char*>(reinterpret_cast<const char*>(A.X) + (int64_t)j0 * col_bytes), 0, (int)nrec, 0x00020000);
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (lim[c] > 0)
+          x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
+        else
+          x[l][c] = S::zero();
+      }
+    }
+    cf.load(A.rdn, A.gram, A.cross, bi, lane);
+  };
+
+  auto finalize = [&](int sdone, bool conv, int64_t cols, double nrm2) {
+    if (wg == 0 && tid == 0) {
+      A.ctl[CTL_SWEEPS] = sdone;
+      A.ctl[CTL_CONVERGED] = conv ? 1 : 0;
+      A.ctl[CTL_DONE] = 1;
+      A.ctl64[C64_COLS] = cols;
+      A.fstat[0] = nrm2;
+    }
+  };
+
+  // Grid reduction of exchange `sq` (published by every workgroup) into tot.
+  // Returns false on timeout.
+  auto poll = [&](uint32_t sq, double (&tot)[NV]) -> bool {
+    const int par = (int)(sq & 1u);
+    const uint64_t* slot_base = A.slots + (int64_t)(sq & 3u) * NV * A.P;
+    const int ncn = (A.P + WAVE - 1) / WAVE;
+    const int ntask = NV * ncn;
+    bool timed_out = false;
+    for (int t0 = wave; t0 < ntask; t0 += NW * MAXT) {
+      uint64_t w[MAXT];
+#pragma unroll
+      for (int q = 0; q < MAXT; ++q) {
+        const int t = t0 + q * NW;
+        const int l = t / ncn, c = t - l * ncn, idx = c * WAVE + lane;
+        const bool live = t < ntask && idx < A.P;
+        w[q] = live ? peek(slot_base + (int64_t)l * A.P + idx) : ((uint64_t)sq << 32);
+      }
+      uint64_t tstart = 0;
+      for (int spin = 0;; ++spin) {
+        bool ready = true;
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) ready = ready && ((uint32_t)(w[q] >> 32) == sq);
+        if (ready) break;
+        if (spin == 0) tstart = now_ticks();
+        else if (now_ticks() - tstart > A.timeout_ticks) {
+          timed_out = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) {
+          if ((uint32_t)(w[q] >> 32) != sq) {
+            const int t = t0 + q * NW;
+            const int l = t / ncn, c = t - l * ncn, idx = c * WAVE + lane;
+            w[q] = peek(slot_base + (int64_t)l * A.P + idx);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < MAXT; ++q) {
+        const int t = t0 + q * NW;
+        if (t < ntask) {
+          const int l = t / ncn, c = t - l * ncn, idx = c * WAVE + lane;
+          const double v = wave_sum(idx < A.P ? (double)__uint_as_float((uint32_t)w[q]) : 0.0);
+          if (lane == 0) gsum[par][l][c] = v;
+        }
+      }
+    }
+    if (timed_out) sflag = 1;
+    __syncthreads();
+    if (sflag) {
+      if (tid == 0) store_flag(&A.ctl[CTL_ERR], ERR_TIMEOUT);
+      return false;
+    }
+#pragma unroll
+    for (int l = 0; l < NV; ++l) {
+      double sacc = 0.0;
+      for (int c = 0; c < ncn; ++c) sacc += gsum[par][l][c];
+      tot[l] = uniform_f64(sacc);
+    }
+    return true;
+  };
+
+  // In-block forward substitution, optionally after removing the part of the
+  // dots due to the previous block's not yet applied update.
+  auto solve_block = [&](const double (&tot)[NV], const CF& cf, bool lagged, const double (&dprev)[B],
+                         double (&da)[B]) {
+    double g[B];
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      double acc = tot[l];
+      if (lagged) {
+#pragma unroll
+        for (int i = 0; i < B; ++i) acc -= cf.get(B + CF::NG + l * B + i) * dprev[i];
+      }
+      g[l] = acc;
+    }
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      double acc = g[l];
+#pragma unroll
+      for (int i = 0; i < l; ++i) acc -= cf.get(B + l * (l - 1) / 2 + i) * da[i];
+      da[l] = uniform_f64(acc * cf.get(l));
+    }
+  };
+
+  auto apply = [&](const raw (&x)[B][R], const double (&da)[B], int j0) {
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      const float f = (float)da[l];
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) e[c][i] = fmaf(-f, S::get(x[l][c], i), e[c][i]);
+    }
+    if (tid < B) {
+      const int64_t j = j0 + tid;
+      if (j < n && (int)(j % A.P) == wg) {
+        double d = 0.0;
+#pragma unroll
+        for (int l = 0; l < B; ++l) if (tid == l) d = da[l];
+        (void)__hip_atomic_fetch_add(&A.a64[j], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  };
+
+  int bi = (int)(A.blk_begin % nb);
+  int sdone = (int)(A.blk_begin / nb);
+  uint32_t seq = (uint32_t)(A.blk_begin + 1);
+  // pipeline state: the pending (published, not yet applied) block
+  bool pending = false, pend_lag = false;
+  int pend_bi = 0;
+  double dprev[B];  // da of the block before the pending one
+#pragma unroll
+  for (int l = 0; l < B; ++l) dprev[l] = 0.0;
+
+  // Wait for the pending block's reduction and apply its update.
+  auto retire = [&](const raw (&xp)[B][R], const CF& cp) -> bool {
+    double tot[NV];
+    if (!poll(seq - 1, tot)) return false;
+    if (!(tot[B] <= DBL_MAX)) {
+      if (wg == 0 && tid == 0) store_flag(&A.ctl[CTL_ERR], ERR_NONFINITE);
+      finalize(sdone, false, (int64_t)sdone * n + (int64_t)pend_bi * B, tot[B]);
+      return false;
+    }
+    double da[B];
+    solve_block(tot, cp, pend_lag, dprev, da);
+    apply(xp, da, pend_bi * B);
+#pragma unroll
+    for (int l = 0; l < B; ++l) dprev[l] = da[l];
+    pending = false;
+    return true;
+  };
+
+  // One step; returns true when the kernel must stop.
+  auto step = [&](raw (&prv)[B][R], raw (&cur)[B][R], raw (&pf)[B][R], CF& cprv, CF& ccur, CF& cpf,
+                  bool has_pf) -> bool {
+    const int j0 = bi * B;
+    int pbi = bi + 2;
+    while (pbi >= nb) pbi -= nb;
+    if (bi == 0 && pending) {
+      if (!retire(prv, cprv)) return true;
+    }
+    float p[NV];
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        if (lim[c] < VEC) cur[l][c] = mask_chunk<S>(cur[l][c], lim[c]);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(cur[l][c], i), e[c][i], acc);
+      }
+      p[l] = acc;
+    }
+    {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc = fmaf(e[c][i], e[c][i], acc);
+      p[B] = acc;
+    }
+    bool aborting = false;
+    if (bi == 0 && wg == 0 && tid == 0 && load_flag(&A.ctl[CTL_ABORT]) != 0) {
+      p[B] = __int_as_float(0x7fc00000);
+      aborting = true;
+    }
+    const int rpar = (int)(seq & 1u);
+#pragma unroll
+    for (int l = 0; l < NV; ++l) {
+      const float v = wave_sum(p[l]);
+      if (lane == 0) red[rpar][wave][l] = v;
+    }
+    __syncthreads();
+    if (tid < NV) {
+      float sacc = 0.f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) sacc += red[rpar][w][tid];
+      publish(A.slots + (int64_t)(seq & 3u) * NV * A.P + (int64_t)tid * A.P + wg, seq, sacc);
+    }
+    const bool lag_now = pending;  // the dots just published lack the pending block's update
+
+    if (bi == 0) {
+      // Synchronous step at a sweep boundary: exact residual, exact norm.
+      double tot[NV];
+      if (!poll(seq, tot)) return true;
+      if (has_pf) load_block(pf, cpf, pbi);
+      const double nrm2 = tot[B], nrm = sqrt(nrm2);
+      if (!(nrm2 <= DBL_MAX)) {
+        if (wg == 0 && tid == 0) store_flag(&A.ctl[CTL_ERR], aborting ? ERR_ABORTED : ERR_NONFINITE);
+        finalize(sdone, false, (int64_t)sdone * n, nrm2);
+        return true;
+      }
+      if (wg == 0 && tid == 0) { A.hist[sdone] = nrm; A.fstat[1] = nrm; }
+      bool stop = false, conv = false;
+      if (A.stop != STOP_NONE && nrm2 == 0.0) stop = conv = true;
+      else if (A.stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < A.tol * nrm) stop = conv = true;
+      else if (A.stop == STOP_REL_RESID && nrm < A.tol * ynorm) stop = conv = true;
+      if (!stop && sdone >= A.max_sweeps) stop = true;
+      prev_norm = nrm;
+      if (stop) { finalize(sdone, conv, (int64_t)sdone * n, nrm2); return true; }
+      double da[B];
+      const double zero[B] = {};
+      solve_block(tot, ccur, false, zero, da);
+      apply(cur, da, j0);
+#pragma unroll
+      for (int l = 0; l < B; ++l) dprev[l] = da[l];
+      pending = false;
+    } else {
+      if (pending) {
+        if (!retire(prv, cprv)) return true;
+      }
+      if (has_pf) load_block(pf, cpf, pbi);
+      pending = true;
+      pend_lag = lag_now;
+      pend_bi = bi;
+    }
+    bi = bi + 1 == nb ? 0 : bi + 1;
+    if (bi == 0) ++sdone;
+    ++seq;
+    return false;
+  };
+
+  if (nblocks > 0) load_block(x0, c0, bi);
+  if (nblocks > 1) load_block(x1, c1, bi + 1 == nb ? 0 : bi + 1);
+  __syncthreads();
+  int64_t k = 0;
+  bool stopped = false;
+  while (k < nblocks) {
+    if (step(x3, x0, x2, c3, c0, c2, k + 2 < nblocks)) { stopped = true; break; }
     if (++k >= nblocks) break;
-    if (step(xb, xa, cb, ca, k + 1 < nblocks)) break;
+    if (step(x0, x1, x3, c0, c1, c3, k + 2 < nblocks)) { stopped = true; break; }
+    if (++k >= nblocks) break;
+    if (step(x1, x2, x0, c1, c2, c0, k + 2 < nblocks)) { stopped = true; break; }
+    if (++k >= nblocks) break;
+    if (step(x2, x3, x1, c2, c3, c1, k + 2 < nblocks)) { stopped = true; break; }
     ++k;
+  }
+  // A launch that ends inside a sweep retires its last block before exiting.
+  if (!stopped && pending) {
+    switch ((int)((k - 1) & 3)) {
+      case 0: retire(x0, c0); break;
+      case 1: retire(x1, c1); break;
+      case 2: retire(x2, c2); break;
+      default: retire(x3, c3); break;
+    }
   }
 #pragma unroll
   for (int c = 0; c < R; ++c)
@@ -513,20 +1186,33 @@ __global__ void __launch_bounds__(BT) k_batched(BatchArgs A) {
 // --------------------------------------------------------------------------
 // Variant registry
 // --------------------------------------------------------------------------
-#define HPSCD_SWEEP_VARIANTS(X_)                                                  \
-  X_(F32, 1024, 1, 1, true) X_(F32, 1024, 1, 2, true) X_(F32, 1024, 1, 4, true)   \
-  X_(F32, 1024, 1, 8, true)                                                       \
-  X_(F32, 512, 2, 2, true) X_(F32, 512, 2, 4, true) X_(F32, 512, 2, 8, true)      \
-  X_(BF16, 512, 1, 4, true) X_(BF16, 512, 1, 8, true) X_(BF16, 1024, 1, 4, true)  \
-  X_(F32, 256, 1, 1, true) X_(F32, 256, 1, 2, true) X_(F32, 256, 1, 4, true)      \
-  X_(F32, 256, 1, 8, true)                                                         \
-  X_(F32, 256, 2, 1, false) X_(F32, 256, 2, 2, false) X_(F32, 256, 2, 4, false)   \
-  X_(F32, 256, 2, 8, false)                                                        \
-  X_(F32, 256, 4, 1, false) X_(F32, 256, 4, 2, false) X_(F32, 256, 4, 4, false)   \
-  X_(F32, 256, 4, 8, false)                                                        \
-  X_(BF16, 1024, 1, 1, true) X_(BF16, 1024, 1, 8, true)                           \
-  X_(BF16, 256, 1, 1, false) X_(BF16, 256, 1, 4, false) X_(BF16, 256, 1, 8, false)\
-  X_(BF16, 256, 2, 1, false) X_(BF16, 256, 2, 4, false) X_(BF16, 256, 2, 8, false)
+#define HPSCD_SWEEP_VARIANTS(X_)                                                              \
+  X_(F32, 1024, 1, 1, true, 2) X_(F32, 1024, 1, 2, true, 2) X_(F32, 1024, 1, 4, true, 2)      \
+  X_(F32, 1024, 1, 4, true, 3) X_(F32, 512, 2, 4, true, 3) X_(F32, 512, 2, 8, true, 3)        \
+  X_(F32, 512, 2, 2, true, 2) X_(F32, 512, 2, 4, true, 2) X_(F32, 512, 2, 8, true, 2)         \
+  X_(F32, 256, 4, 8, true, 2) X_(F32, 256, 4, 8, true, 3) X_(F32, 256, 4, 4, true, 3)         \
+  X_(BF16, 512, 1, 4, true, 2) X_(BF16, 512, 1, 8, true, 2) X_(BF16, 1024, 1, 4, true, 2)     \
+  X_(BF16, 512, 1, 8, true, 3) X_(BF16, 256, 2, 8, true, 3)                                    \
+  X_(F32, 256, 1, 1, true, 2) X_(F32, 256, 1, 2, true, 2) X_(F32, 256, 1, 4, true, 2)         \
+  X_(F32, 256, 1, 8, true, 2)                                                                  \
+  X_(F32, 256, 2, 1, false, 2) X_(F32, 256, 2, 2, false, 2) X_(F32, 256, 2, 4, false, 2)      \
+  X_(F32, 256, 2, 8, false, 2)                                                                 \
+  X_(F32, 256, 4, 1, false, 2) X_(F32, 256, 4, 2, false, 2) X_(F32, 256, 4, 4, false, 2)      \
+  X_(F32, 256, 4, 8, false, 2)                                                                 \
+  X_(BF16, 1024, 1, 1, true, 2) X_(BF16, 1024, 1, 8, true, 2)                                 \
+  X_(BF16, 256, 1, 1, false, 2) X_(BF16, 256, 1, 4, false, 2) X_(BF16, 256, 1, 8, false, 2)   \
+  X_(BF16, 256, 2, 1, false, 2) X_(BF16, 256, 2, 4, false, 2) X_(BF16, 256, 2, 8, false, 2)
+
+#define HPSCD_PIPE_VARIANTS(X_)                                                   \
+  X_(F32, 1024, 1, 2) X_(F32, 512, 2, 2) X_(F32, 512, 2, 4) X_(F32, 256, 4, 4)    \
+  X_(F32, 256, 1, 4) X_(F32, 256, 2, 4)                                             \
+  X_(BF16, 512, 1, 4) X_(BF16, 256, 2, 4)
+
+#define HPSCD_WS_VARIANTS(X_)                                                                     \
+  X_(F32, 512, 2, 4, 3) X_(F32, 512, 2, 8, 2) X_(F32, 512, 2, 4, 2) X_(F32, 256, 4, 4, 3)          \
+  X_(F32, 256, 4, 8, 2) X_(F32, 256, 4, 8, 3) X_(F32, 1024, 1, 4, 2) X_(F32, 1024, 1, 2, 2)        \
+  X_(F32, 1024, 1, 4, 3) X_(F32, 256, 1, 4, 2) X_(F32, 256, 1, 8, 2)                              \
+  X_(BF16, 512, 1, 8, 2) X_(BF16, 512, 1, 4, 3) X_(BF16, 512, 1, 8, 3) X_(BF16, 256, 2, 8, 3)
 
 #define HPSCD_IS_BF16_F32 false
 #define HPSCD_IS_BF16_BF16 true
@@ -534,38 +1220,54 @@ __global__ void __launch_bounds__(BT) k_batched(BatchArgs A) {
 struct Variant {
   int T, R, B;
   bool bf16, grid;
+  int D;           // 2, 3: prefetch ring; 4: pipelined; 12, 13: warp-specialised with ring 2, 3
   const void* fn;
+  int threads;     // launch width
 };
 
-#define HPSCD_ENTRY(S, T, R, B, G) \
-  {T, R, B, HPSCD_IS_BF16_##S, G, reinterpret_cast<const void*>(&k_sweep<S, T, R, B, G>)},
-static const Variant kVariants[] = {HPSCD_SWEEP_VARIANTS(HPSCD_ENTRY)};
+#define HPSCD_ENTRY(S, T, R, B, G, D) \
+  {T, R, B, HPSCD_IS_BF16_##S, G, D, reinterpret_cast<const void*>(&k_sweep<S, T, R, B, G, D>), T},
+#define HPSCD_WENTRY(S, T, R, B, D) \
+  {T, R, B, HPSCD_IS_BF16_##S, true, 10 + D, reinterpret_cast<const void*>(&k_sweep_ws<S, T, R, B, D>), T + WAVE},
+#define HPSCD_PENTRY(S, T, R, B) \
+  {T, R, B, HPSCD_IS_BF16_##S, true, 4, reinterpret_cast<const void*>(&k_sweep_pipe<S, T, R, B>), T},
+static const Variant kVariants[] = {HPSCD_SWEEP_VARIANTS(HPSCD_ENTRY) HPSCD_PIPE_VARIANTS(HPSCD_PENTRY)
+                                        HPSCD_WS_VARIANTS(HPSCD_WENTRY)};
 
-static const Variant* find_variant(int T, int R, int B, bool bf16, bool grid) {
+// The deepest prefetch ring built for the shape (D = 0: any).
+static const Variant* find_variant(int T, int R, int B, bool bf16, bool grid, int D = 0) {
+  const Variant* best = nullptr;
   for (const Variant& v : kVariants)
-    if (v.T == T && v.R == R && v.B == B && v.bf16 == bf16 && v.grid == grid) return &v;
-  return nullptr;
+    if (v.T == T && v.R == R && v.B == B && v.bf16 == bf16 && v.grid == grid && (D == 0 || v.D == D))
+      if (!best || v.D > best->D) best = &v;
+  return best;
 }
 
-bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid) {
-  return find_variant(T, R, B, bf16, grid) != nullptr;
+bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid, int D) {
+  return find_variant(T, R, B, bf16, grid, D) != nullptr;
 }
 
-int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid) {
-  const Variant* v = find_variant(T, R, B, bf16, grid);
+int sweep_max_workgroups(int T, int R, int B, bool bf16, bool grid, int D) {
+  const Variant* v = find_variant(T, R, B, bf16, grid, D);
+  if (!v) return 0;
+  return v->D >= 10 ? 256 : 512;
+}
+
+int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid, int D) {
+  const Variant* v = find_variant(T, R, B, bf16, grid, D);
   if (!v) return 0;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn, T, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn, v->threads, 0) != hipSuccess) return 0;
   return nb;
 }
 
-hipError_t launch_sweep(int T, int R, int B, bool bf16, bool grid, const SolveArgs& a, hipStream_t s,
+hipError_t launch_sweep(int T, int R, int B, bool bf16, bool grid, int D, const SolveArgs& a, hipStream_t s,
                         bool cooperative) {
-  const Variant* v = find_variant(T, R, B, bf16, grid);
+  const Variant* v = find_variant(T, R, B, bf16, grid, D);
   if (!v) return hipErrorInvalidValue;
   SolveArgs args = a;
   void* kargs[] = {&args};
-  const dim3 g(grid ? (unsigned)a.P : 1u), b((unsigned)T);
+  const dim3 g(grid ? (unsigned)a.P : 1u), b((unsigned)v->threads);
   if (cooperative) return hipLaunchCooperativeKernel(v->fn, g, b, kargs, 0, s);
   return hipLaunchKernel(v->fn, g, b, kargs, 0, s);
 }

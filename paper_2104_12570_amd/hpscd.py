@@ -50,7 +50,7 @@ _NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENONFINITE", 5: "
 class Opts(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int32), ("stop", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("check_cols", ctypes.c_int64), ("refresh_cols", ctypes.c_int64), ("block", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("team_threads", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("team_threads", ctypes.c_int32), ("depth", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -111,12 +111,13 @@ def last_error() -> str:
 
 
 def make_opts(max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols=0, refresh_cols=0, block=0, flags=0,
-              team_threads=0) -> Opts:
+              team_threads=0, depth=0) -> Opts:
     o = Opts()
     _lib.hpscd_default_opts(ctypes.byref(o))
     o.max_sweeps, o.stop, o.tol = int(max_sweeps), int(stop), float(tol)
     o.check_cols, o.refresh_cols, o.block, o.flags = int(check_cols), int(refresh_cols), int(block), int(flags)
     o.team_threads = int(team_threads)
+    o.depth = int(depth)
     return o
 
 
@@ -172,7 +173,7 @@ class Result:
 
 
 def solve(Xt, y, a0=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols=0, block=0, flags=0,
-          team_threads=0, want_hist=True) -> Result:
+          team_threads=0, depth=0, want_hist=True) -> Result:
     """Solve X·a = y (Algorithm 1, single precision) on the GPU.
 
     Xt: (n, ldx) float32 CUDA tensor (column j of X in Xt[j, :m]); y: (m,)."""
@@ -183,7 +184,7 @@ def solve(Xt, y, a0=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols
     n, ldx = Xt.shape
     m = y.numel()
     a = torch.empty(n, dtype=torch.float32, device=Xt.device)
-    opts = make_opts(max_sweeps, stop, tol, check_cols, 0, block, flags, team_threads)
+    opts = make_opts(max_sweeps, stop, tol, check_cols, 0, block, flags, team_threads, depth)
     hist = np.full(max_sweeps + 1, np.nan) if want_hist else None
     info = Info()
     _check(_lib.hpscd_solve_f32(context(Xt.device.index), m, n, _ptr(Xt), ldx, _ptr(y), _ptr(a0),
@@ -206,7 +207,7 @@ def convert_bf16(Xt):
 
 
 def solve_bf16(Xb, Xt32, y, a0=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols=0, refresh_cols=0,
-               block=0, flags=0, want_hist=True) -> Result:
+               block=0, flags=0, team_threads=0, depth=0, want_hist=True) -> Result:
     """bfloat16-storage form: sweeps read Xb, refreshes and the final check read Xt32."""
     torch = _torch()
     _need_cuda(Xb, "Xb", torch.bfloat16)
@@ -217,7 +218,7 @@ def solve_bf16(Xb, Xt32, y, a0=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0,
     ldx = Xt32.shape[1]
     m = y.numel()
     a = torch.empty(n, dtype=torch.float32, device=Xb.device)
-    opts = make_opts(max_sweeps, stop, tol, check_cols, refresh_cols, block, flags)
+    opts = make_opts(max_sweeps, stop, tol, check_cols, refresh_cols, block, flags, team_threads, depth)
     hist = np.full(max_sweeps + 1, np.nan) if want_hist else None
     info = Info()
     _check(_lib.hpscd_solve_bf16(context(Xb.device.index), m, n, _ptr(Xb), ldxb, _ptr(Xt32), ldx, _ptr(y),

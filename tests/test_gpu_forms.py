@@ -123,3 +123,17 @@ def test_batched_stop_and_warm_start(lib):
     r2 = lib.solve_batched(dev(b.Xpool), dev(b.ypool), b.table, a0pool=a0, max_sweeps=1, want_hist=True)
     for i in range(b.count):
         assert r2.hist[i][1] <= r2.hist[i][0] * (1 + 1e-6)
+
+
+def test_bf16_pipelined_refresh_mid_sweep(lib):
+    """Refresh every 16 column steps on a 32-column system: each launch ends
+    inside a sweep and retires its last pipelined block before the refresh."""
+    s = gen.tall_large(m=100_000, n=32, seed=9)
+    X32 = dev(s.Xt)
+    Xb = lib.convert_bf16(X32)
+    say("bf16 pipelined")
+    r = lib.solve_bf16(Xb, X32, dev(s.y), max_sweeps=4, refresh_cols=16, block=4, depth=4)
+    ref = oracle.solve_bf16_refresh(s.Xt, s.y, s.m, max_sweeps=4, refresh_cols=16)
+    assert r.info["refreshes"] == ref.refreshes == 8
+    assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5, r.info
+    assert np.all(np.abs(np.asarray(r.hist) - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0])

@@ -113,6 +113,8 @@ def test_tall_large_full_size_two_sweeps(lib):
     say("tall_large full size")
     r, ref = check(lib, s, 2)
     say("info", r.info)
+    for kind in (12, 13):
+        check(lib, s, 2, block=4, depth=kind)
 
 
 def test_wide_workgroup(lib):
@@ -213,3 +215,32 @@ def test_residual_f64(lib):
     ref = oracle.residual(s.Xt, s.y, s.m, a.astype(np.float64))
     assert nrm == pytest.approx(np.linalg.norm(ref), rel=1e-12)
     np.testing.assert_allclose(e.cpu().numpy(), ref.astype(np.float32), rtol=1e-6, atol=1e-6)
+
+
+# ------------------------------------------------------------ pipelined grid
+
+@pytest.mark.parametrize("block,kind", [(2, 4), (4, 4), (4, 12), (4, 13), (8, 12)])
+def test_grid_kernel_kinds_match_oracle(lib, block, kind):
+    """Every grid kernel kind (pipelined reductions with the cross-block Gram
+    correction; warp-specialised with a two- or three-block ring) produces the
+    iterates of Algorithm 1 (n not a multiple of the block, ragged rows)."""
+    s = gen.tall_large(m=300_003, n=37, seed=13, pad=np.nan)
+    say("grid kind", block, kind)
+    r, ref = check(lib, s, 6, block=block, depth=kind)
+    assert r.info["block_used"] == block and r.info["team_wgs"] > 1
+
+
+def test_pipelined_grid_stop_rule(lib):
+    s = gen.tall_large(m=250_000, n=48, seed=21)
+    say("pipelined stop")
+    r = run(lib, s, 100, block=4, depth=4, stop=lib.STOP_REL_CHANGE, tol=1e-6)
+    ref = oracle.solve(s.Xt, s.y, s.m, max_sweeps=100, tol=1e-6, stop=oracle.STOP_REL_CHANGE)
+    assert r.info["converged"] == 1 and abs(r.info["sweeps_done"] - ref.sweeps) <= 1
+    check(lib, s, r.info["sweeps_done"], block=4, depth=4)
+
+
+def test_pipelined_grid_warm_start(lib):
+    s = gen.tall_large(m=200_000, n=24, seed=5)
+    a0 = np.random.default_rng(2).standard_normal(s.n).astype(np.float32)
+    say("pipelined warm")
+    check(lib, s, 3, a0=a0, block=4, depth=4)
