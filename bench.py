@@ -51,6 +51,20 @@ def cpu_baseline(s, budget_s: float = 15.0):
             "sample": f"{sweeps} sweep(s) of the {s.m}x{s.n} system, FP64 NumPy, 1 thread, {dt:.1f} s"}
 
 
+def measured_traffic(key: str, sweeps: float):
+    """HBM bytes per launch of the sweep kernel from the committed counter runs
+    (profiles/traffic.json), or None when the kernel source changed since."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[key]
+        src = open(os.path.join(ROOT, "paper_2104_12570_amd", "csrc", "hpscd_sweep.hip"), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["hbm_bytes_per_sweep"] * sweeps
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +76,8 @@ def main():
     ap.add_argument("--fixed-sweeps", type=int, default=0, help="run exactly this many sweeps (no stop test)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -77,6 +93,13 @@ def main():
     Xt = torch.from_numpy(s.Xt).cuda()
     y = torch.from_numpy(s.y).cuda()
     torch.cuda.synchronize()
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # reads 1 GiB and writes 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
     if args.fixed_sweeps > 0:
         kw = dict(max_sweeps=args.fixed_sweeps, stop=hpscd.STOP_NONE)
     else:
@@ -128,7 +151,9 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic("k_sweep_f32_tall_1000000x256", sweeps)
+            if (s.m, s.n, args.fixed_sweeps) == (1_000_000, 256, 0) else None,
             "kernel": "k_sweep (persistent grid)", "alg_bytes_per_launch": alg_bytes,
             "launch_ms": sweep_ms,
         },
