@@ -136,11 +136,14 @@ hpscd_status hpscd_residual_f64(hpscd_ctx* ctx, int64_t m, int64_t n, const floa
 /* Batched form: `count` independent systems in one persistent launch.
  * sys[i] gives system i's sizes and element offsets into the pools; every
  * system needs x_off % 4 == 0, ldx % 4 == 0, ldx >= m, 1 <= m <= 8192.
+ * sys[i].tol > 0 replaces opts->tol for that system's stop rule (0: use
+ * opts->tol); it must be finite and >= 0.
  * a0pool: NULL or initial guesses at a_off.  apool: results at a_off.
  * hist: NULL or count*(max_sweeps+1) doubles (row i for system i).
  * sweeps_done, converged, final_rel_resid: NULL or count entries (host). */
 typedef struct {
   int64_t m, n, x_off, ldx, y_off, a_off;
+  double tol;
 } hpscd_sys;
 
 hpscd_status hpscd_solve_batched_f32(hpscd_ctx* ctx, int32_t count, const hpscd_sys* sys, const float* Xpool,
@@ -156,6 +159,36 @@ hpscd_status hpscd_autotune_batched(hpscd_ctx* ctx, int32_t count, const hpscd_s
 /* Ask a running solve on this context to stop at its next sweep boundary;
  * that solve returns HPSCD_EABORTED.  Safe to call from another thread. */
 hpscd_status hpscd_abort(hpscd_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start: a multilayer perceptron in -> h1 -> h2 -> out with the
+ * exact GELU (0.5 z (1 + erf(z / sqrt 2))) after both hidden layers and a
+ * linear output, trained with Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the
+ * mean squared error L = sum_{b,k} (o_bk - t_bk)^2 / (batch * out).  It maps a
+ * system's parameters to a predicted solution, used as the initial guess a0
+ * of Algorithm 1 (the algorithm's first line allows any initial guess).
+ * Parameter vector (FP32, device): W1[h1][in], b1[h1], W2[h2][h1], b2[h2],
+ * W3[out][h2], b3[out] (row o of a W holds the weights of output unit o).
+ * x, target, y, flat and grad_flat are device pointers; rows are row-major
+ * ([batch][in], [batch][out]).  All work is queued on `stream`; calls that
+ * fill loss_out (host) wait for it.
+ * ------------------------------------------------------------------------- */
+typedef struct hpscd_mlp hpscd_mlp;
+
+hpscd_status hpscd_mlp_create(int device, int in, int h1, int h2, int out, hpscd_mlp** res);
+void hpscd_mlp_destroy(hpscd_mlp* net);
+int64_t hpscd_mlp_num_params(const hpscd_mlp* net);
+/* Copy parameters in (and reset the Adam state) / out. */
+hpscd_status hpscd_mlp_set_params(hpscd_mlp* net, const float* flat, void* stream);
+hpscd_status hpscd_mlp_get_params(hpscd_mlp* net, float* flat, void* stream);
+/* y[batch][out] = net(x[batch][in]). */
+hpscd_status hpscd_mlp_forward(hpscd_mlp* net, int batch, const float* x, float* y, void* stream);
+/* Gradient of L at the current parameters into grad_flat (NULL: kept inside). */
+hpscd_status hpscd_mlp_grads(hpscd_mlp* net, int batch, const float* x, const float* target, float* grad_flat,
+                             float* loss_out, void* stream);
+/* One Adam step on L for this batch; loss_out (host, NULL ok) gets L before the step. */
+hpscd_status hpscd_mlp_train_step(hpscd_mlp* net, int batch, const float* x, const float* target, float lr,
+                                  float* loss_out, void* stream);
 
 /* Message of the last failure on this host thread ("" if none). */
 const char* hpscd_last_error(void);

@@ -177,12 +177,16 @@ def solve_bf16_refresh(Xt32, y, m=None, a0=None, max_sweeps=1, tol=0.0,
                  Xt_refresh=Xt32, refresh_cols=refresh_cols)
 
 
-def solve_batch(batch, a0pool=None, **kw):
-    """Solve every system of a packed ``workloads.Batch`` independently."""
+def solve_batch(batch, a0pool=None, tols=None, **kw):
+    """Solve every system of a packed ``workloads.Batch`` independently;
+    ``tols[i] > 0`` replaces ``tol`` for system i."""
     out = []
     for i in range(batch.count):
         s = batch.system(i)
         a_off = int(batch.table[i, 5])
         a0 = None if a0pool is None else a0pool[a_off: a_off + s.n]
-        out.append(solve(s.Xt, s.y, s.m, a0, **kw))
+        kwi = dict(kw)
+        if tols is not None and tols[i] > 0:
+            kwi["tol"] = float(tols[i])
+        out.append(solve(s.Xt, s.y, s.m, a0, **kwi))
     return out

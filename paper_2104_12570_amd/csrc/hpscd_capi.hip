@@ -17,8 +17,12 @@
 using namespace hpscd;
 
 namespace {
-
 thread_local std::string g_err;
+}
+
+void hpscd::set_last_error(const char* msg) { g_err = msg; }
+
+namespace {
 
 hpscd_status fail(hpscd_status st, const char* fmt, ...) {
   char buf[512];
@@ -511,6 +515,7 @@ hpscd_status validate_batch(int32_t count, const hpscd_sys* sys, const float* Xp
     if (s.ldx < s.m || s.ldx % 4 != 0) return fail(HPSCD_EINVAL, "system %d: need ldx >= m and ldx %% 4 == 0", i);
     if (s.x_off < 0 || s.x_off % 4 != 0) return fail(HPSCD_EINVAL, "system %d: x_off must be >= 0 and %% 4 == 0", i);
     if (s.y_off < 0 || s.a_off < 0) return fail(HPSCD_EINVAL, "system %d: negative offset", i);
+    if (!(s.tol >= 0.0) || !std::isfinite(s.tol)) return fail(HPSCD_EINVAL, "system %d: tol must be finite and >= 0", i);
   }
   return validate_opts(o);
 }
@@ -518,14 +523,14 @@ hpscd_status validate_batch(int32_t count, const hpscd_sys* sys, const float* Xp
 // Work items in longest-processing-time order: systems that fit one wave are
 // grouped four to an item by decreasing size; larger systems get a whole
 // workgroup.  The queue hands items out in this order.
-void plan_batch(int32_t count, const hpscd_sys* sys, int B, int hist_len, BatchPlan* bp) {
+void plan_batch(int32_t count, const hpscd_sys* sys, int B, int hist_len, double tol, BatchPlan* bp) {
   bp->sd.resize(count);
   bp->blk_first.resize(count);
   int64_t g = 0, blk = 0;
   for (int32_t i = 0; i < count; ++i) {
     const hpscd_sys& s = sys[i];
     const int64_t nb = (s.n + B - 1) / B;
-    bp->sd[i] = SysDesc{s.m, s.n, s.x_off, s.ldx, s.y_off, s.a_off, g, (int64_t)i * hist_len};
+    bp->sd[i] = SysDesc{s.m, s.n, s.x_off, s.ldx, s.y_off, s.a_off, g, (int64_t)i * hist_len, s.tol > 0.0 ? s.tol : tol};
     bp->blk_first[i] = blk;
     g += nb * B;
     blk += nb;
@@ -571,7 +576,7 @@ hpscd_status solve_batched(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, co
   HIP_TRY(hipSetDevice(c->device));
   const int hist_len = o->max_sweeps + 1;
   BatchPlan bp;
-  plan_batch(count, sys, B, hist_len, &bp);
+  plan_batch(count, sys, B, hist_len, o->tol, &bp);
   const int nitems = (int)bp.items.size();
   hpscd_status rc;
   const size_t sys_bytes = bp.sd.size() * sizeof(SysDesc);

@@ -36,6 +36,7 @@ struct SysDesc {
   int64_t m, n, x_off, ldx, y_off, a_off;
   int64_t g_off;          // offset of this system's rdn/gram region
   int64_t h_off;          // offset of this system's hist region
+  double tol;             // stop tolerance of this system
 };
 
 // One unit of batched work: a system solved by the whole workgroup, or up to
@@ -65,6 +66,9 @@ struct BatchArgs {
   double tol;
   const double* ynorm2;    // [count] ||y_i||^2
 };
+
+// Message returned by hpscd_last_error() on this host thread.
+void set_last_error(const char* msg);
 
 // Kernel launchers (return hipError_t of the launch).
 // D: kernel kind: 2, 3 = prefetch ring of 2 or 3 blocks; 4 = pipelined reductions;

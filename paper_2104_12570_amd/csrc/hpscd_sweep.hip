@@ -1121,8 +1121,8 @@ __device__ inline void team_solve(const BatchArgs& A, int sidx, int ttid, float 
       bool stop = false, conv = false;
       if (!(nrm2 <= DBL_MAX)) stop = true;
       else if (A.stop != STOP_NONE && nrm2 == 0.0) stop = conv = true;
-      else if (A.stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < A.tol * nrm) stop = conv = true;
-      else if (A.stop == STOP_REL_RESID && nrm < A.tol * ynorm) stop = conv = true;
+      else if (A.stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < sd.tol * nrm) stop = conv = true;
+      else if (A.stop == STOP_REL_RESID && nrm < sd.tol * ynorm) stop = conv = true;
       if (!stop && sdone >= A.max_sweeps) stop = true;
       prev_norm = nrm;
       if (stop) {

@@ -66,7 +66,8 @@ class Info(ctypes.Structure):
 
 class Sys(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("x_off", ctypes.c_int64),
-                ("ldx", ctypes.c_int64), ("y_off", ctypes.c_int64), ("a_off", ctypes.c_int64)]
+                ("ldx", ctypes.c_int64), ("y_off", ctypes.c_int64), ("a_off", ctypes.c_int64),
+                ("tol", ctypes.c_double)]
 
 
 _vp, _i64, _i32, _dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
@@ -88,6 +89,16 @@ _SIGS = {
                                                _dp, _IP, _vp]),
     "hpscd_autotune_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Sys), _vp, _vp, _OP, _vp, _vp]),
     "hpscd_abort": (ctypes.c_int, [_vp]),
+    "hpscd_mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(_vp)]),
+    "hpscd_mlp_destroy": (None, [_vp]),
+    "hpscd_mlp_num_params": (_i64, [_vp]),
+    "hpscd_mlp_set_params": (ctypes.c_int, [_vp, _vp, _vp]),
+    "hpscd_mlp_get_params": (ctypes.c_int, [_vp, _vp, _vp]),
+    "hpscd_mlp_forward": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
+    "hpscd_mlp_grads": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_float), _vp]),
+    "hpscd_mlp_train_step": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_float,
+                                            ctypes.POINTER(ctypes.c_float), _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -242,11 +253,16 @@ def residual_f64(Xt, y, a, want_e=False):
     return nrm.value, e
 
 
-def _sys_array(table):
+def _sys_array(table, tols=None):
+    """ctypes array of hpscd_sys from rows (m, n, x_off, ldx, y_off, a_off)
+    and optional per-system tolerances (0 = the call's tol)."""
     table = np.asarray(table, dtype=np.int64).reshape(-1, 6)
+    tols = np.zeros(len(table)) if tols is None else np.asarray(tols, dtype=np.float64).reshape(-1)
+    if len(tols) != len(table):
+        raise ValueError("tols needs one entry per system")
     arr = (Sys * len(table))()
     for i, row in enumerate(table):
-        arr[i] = Sys(*[int(v) for v in row])
+        arr[i] = Sys(*[int(v) for v in row], float(tols[i]))
     return arr
 
 
@@ -261,9 +277,10 @@ class BatchResult:
 
 
 def solve_batched(Xpool, ypool, table, a0pool=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, block=0,
-                  flags=0, a_size=None, want_hist=False) -> BatchResult:
+                  flags=0, a_size=None, want_hist=False, tols=None) -> BatchResult:
     """Solve every system of a packed batch in one persistent launch.
-    ``table[i] = (m, n, x_off, ldx, y_off, a_off)``."""
+    ``table[i] = (m, n, x_off, ldx, y_off, a_off)``; ``tols[i] > 0`` replaces
+    ``tol`` for system i."""
     torch = _torch()
     _need_cuda(Xpool, "Xpool", torch.float32)
     _need_cuda(ypool, "ypool", torch.float32)
@@ -280,7 +297,7 @@ def solve_batched(Xpool, ypool, table, a0pool=None, *, max_sweeps=100, stop=STOP
     fr = np.zeros(count)
     info = Info()
     _check(_lib.hpscd_solve_batched_f32(
-        context(Xpool.device.index), count, _sys_array(table), _ptr(Xpool), _ptr(ypool), _ptr(a0pool),
+        context(Xpool.device.index), count, _sys_array(table, tols), _ptr(Xpool), _ptr(ypool), _ptr(a0pool),
         ctypes.byref(opts), _ptr(a), hist.ctypes.data_as(_dp) if hist is not None else None,
         sw.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
         fr.ctypes.data_as(_dp), ctypes.byref(info), _stream()))
@@ -300,3 +317,75 @@ def autotune_batched(Xpool, ypool, table, *, max_sweeps=100, stop=STOP_NONE, tol
 
 def abort(device: int | None = None):
     _check(_lib.hpscd_abort(context(device)))
+
+
+# ------------------------------------------------------------------ MLP
+class MLP:
+    """Handle of a device-resident perceptron in -> h1 -> h2 -> out (exact
+    GELU on the hidden layers, linear output) with its Adam state.  All
+    arithmetic runs in the library's kernels; tensors are FP32 on the device."""
+
+    def __init__(self, n_in, h1, h2, n_out, device: int | None = None):
+        torch = _torch()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.shape = (int(n_in), int(h1), int(h2), int(n_out))
+        h = _vp()
+        _check(_lib.hpscd_mlp_create(self.device, *self.shape, ctypes.byref(h)))
+        self._h = h
+        self.num_params = int(_lib.hpscd_mlp_num_params(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hpscd_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, t, name, width):
+        torch = _torch()
+        _need_cuda(t, name, torch.float32)
+        if t.dim() != 2 or t.shape[1] != width:
+            raise ValueError(f"{name} must have shape (batch, {width})")
+        return t
+
+    def set_params(self, flat):
+        torch = _torch()
+        _need_cuda(flat, "flat", torch.float32)
+        if flat.numel() != self.num_params:
+            raise ValueError(f"expected {self.num_params} parameters")
+        _check(_lib.hpscd_mlp_set_params(self._h, _ptr(flat), _stream()))
+
+    def get_params(self):
+        torch = _torch()
+        flat = torch.empty(self.num_params, dtype=torch.float32, device=f"cuda:{self.device}")
+        _check(_lib.hpscd_mlp_get_params(self._h, _ptr(flat), _stream()))
+        return flat
+
+    def forward(self, x):
+        torch = _torch()
+        x = self._vec(x, "x", self.shape[0])
+        y = torch.empty(x.shape[0], self.shape[3], dtype=torch.float32, device=x.device)
+        _check(_lib.hpscd_mlp_forward(self._h, x.shape[0], _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def grads(self, x, target):
+        torch = _torch()
+        x = self._vec(x, "x", self.shape[0])
+        target = self._vec(target, "target", self.shape[3])
+        g = torch.empty(self.num_params, dtype=torch.float32, device=x.device)
+        loss = ctypes.c_float()
+        _check(_lib.hpscd_mlp_grads(self._h, x.shape[0], _ptr(x), _ptr(target), _ptr(g), ctypes.byref(loss),
+                                    _stream()))
+        return g, loss.value
+
+    def train_step(self, x, target, lr, want_loss=False):
+        x = self._vec(x, "x", self.shape[0])
+        target = self._vec(target, "target", self.shape[3])
+        loss = ctypes.c_float()
+        _check(_lib.hpscd_mlp_train_step(self._h, x.shape[0], _ptr(x), _ptr(target), float(lr),
+                                         ctypes.byref(loss) if want_loss else None, _stream()))
+        return loss.value if want_loss else None

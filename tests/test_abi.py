@@ -41,8 +41,9 @@ def test_struct_layouts_match_header(hp):
 #include <stddef.h>
 #include "hpscd.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(hpscd_opts), sizeof(hpscd_info), sizeof(hpscd_sys),
-         offsetof(hpscd_opts, tol), offsetof(hpscd_info, final_norm), offsetof(hpscd_info, total_ms));
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(hpscd_opts), sizeof(hpscd_info), sizeof(hpscd_sys),
+         offsetof(hpscd_opts, tol), offsetof(hpscd_info, final_norm), offsetof(hpscd_info, total_ms),
+         offsetof(hpscd_sys, tol));
   return 0;
 }
 '''
@@ -53,7 +54,7 @@ int main(void) {
         subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     assert got == [ctypes.sizeof(hp.Opts), ctypes.sizeof(hp.Info), ctypes.sizeof(hp.Sys),
-                   hp.Opts.tol.offset, hp.Info.final_norm.offset, hp.Info.total_ms.offset]
+                   hp.Opts.tol.offset, hp.Info.final_norm.offset, hp.Info.total_ms.offset, hp.Sys.tol.offset]
 
 
 def test_version(hp):
@@ -111,6 +112,10 @@ def test_batch_validation(hp):
     st = hp._lib.hpscd_solve_batched_f32(None, 1, table, 4096, 64, None, ctypes.byref(o), 128, None, None, None,
                                          None, None, None)
     assert st == hp.EINVAL and "x_off" in hp.last_error()
+    table = hp._sys_array([[100, 10, 0, 100, 0, 0]], tols=[-1.0])
+    st = hp._lib.hpscd_solve_batched_f32(None, 1, table, 4096, 64, None, ctypes.byref(o), 128, None, None, None,
+                                         None, None, None)
+    assert st == hp.EINVAL and "tol" in hp.last_error()
 
 
 def test_create_without_device(hp):
@@ -127,3 +132,13 @@ def test_single_hip_runtime_shared_with_torch(hp):
     maps = hp.hip_runtimes_mapped()
     assert len(maps) == 1
     assert os.path.dirname(torch.__file__) in maps[0]
+
+
+def test_mlp_create_rejects_bad_widths(hp):
+    h = ctypes.c_void_p()
+    assert hp._lib.hpscd_mlp_create(0, 13, 0, 256, 64, ctypes.byref(h)) == hp.EINVAL
+    assert "widths" in hp.last_error()
+    assert hp._lib.hpscd_mlp_create(0, 13, 256, 256, 64, None) == hp.EINVAL
+    assert hp._lib.hpscd_mlp_num_params(None) == 0
+    assert hp._lib.hpscd_mlp_forward(None, 1, 16, 16, None) == hp.EINVAL
+    hp._lib.hpscd_mlp_destroy(None)

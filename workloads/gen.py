@@ -262,15 +262,27 @@ def rbf_system(p: np.ndarray, t: np.ndarray, n: int = 64, ldx: int | None = None
     return System(Xt, y.astype(dtype), m, n, None, dict(workload="rbf"))
 
 
-# Affine standardisation of the 13 parameters from their sampling ranges
-# (uniform on [lo, hi] has mean (lo+hi)/2 and std (hi-lo)/sqrt(12)).
-_RBF_LO = np.array([0.02] + [0.5] * 4 + [1.0] * 4 + [0.0] * 4)
-_RBF_HI = np.array([0.1] + [1.5] * 4 + [8.0] * 4 + [2.0 * math.pi] * 4)
+# Network inputs.  Each sinusoid A sin(2 pi f t + phi) is re-coded by its
+# phasor (A cos phi, A sin phi): y is linear in the phasors, and the code has
+# no jump where phi wraps from 2 pi to 0.  sigma and the sorted f_k are scaled
+# from their sampling ranges (uniform on [lo, hi]: mean (lo+hi)/2, std
+# (hi-lo)/sqrt(12)); A cos phi and A sin phi have mean 0 and std
+# sqrt(E[A^2]/2) = sqrt(13/24) for A ~ U[0.5, 1.5].
+_RBF_LO = np.array([0.02] + [1.0] * 4)
+_RBF_HI = np.array([0.1] + [8.0] * 4)
+_PHASOR_SD = math.sqrt(13.0 / 24.0)
 
 
 def rbf_features(P: np.ndarray) -> np.ndarray:
-    """Network inputs: the 13 parameters standardised by their sampling
-    ranges, FP32, shape (count, 13)."""
+    """Network inputs (count, 13) FP32 from family parameters ``P``:
+    [sigma, f1..f4, A1 cos phi1, A1 sin phi1, ..., A4 cos phi4, A4 sin phi4],
+    each standardised.  A bijective re-coding of the 13 parameters."""
+    P = np.asarray(P, dtype=np.float64)
+    sf = P[:, [0, 5, 6, 7, 8]]
     mu = 0.5 * (_RBF_LO + _RBF_HI)
     sd = (_RBF_HI - _RBF_LO) / math.sqrt(12.0)
-    return ((np.asarray(P) - mu) / sd).astype(np.float32)
+    A, phi = P[:, 1:5], P[:, 9:13]
+    ph = np.empty((len(P), 8))
+    ph[:, 0::2] = A * np.cos(phi)
+    ph[:, 1::2] = A * np.sin(phi)
+    return np.concatenate([(sf - mu) / sd, ph / _PHASOR_SD], axis=1).astype(np.float32)
