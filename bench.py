@@ -12,6 +12,21 @@ object reports the sweep kernel: algorithmic bytes per launch (X read once
 per sweep: sweeps * m * n * 4 bytes) over its HIP-event duration, against the
 8 TB/s HBM peak.  The cpu_baseline object times the FP64 oracle on the host
 on a bounded sample (a few sweeps of the same system).
+
+Other forms (``--form``), each printing one JSON line of its own:
+
+* ``bf16``      the 2000 x 200,000 wide system stored as bfloat16 with FP64
+                refreshes from the FP32 copy, solved to a true relative
+                residual of 1e-6 (stop confirmed on the refreshed residual),
+                beside the plain FP32 solve under the same rule;
+* ``batched``   4096 independent tall systems (m log-uniform in [256, 8192],
+                n in [8, 128]) in one autotuned persistent launch, beside one
+                solve call per system;
+* ``warmstart`` the radial-basis family (m = 4096, n = 64): labels from 100
+                sweeps on 50,000 training systems, network training, then
+                2,000 held-out systems solved from the predicted a0 to the
+                residual that 100 sweeps from zero reach, beside the solve
+                from zero.
 """
 from __future__ import annotations
 
@@ -65,9 +80,179 @@ def measured_traffic(key: str, sweeps: float):
     return rec["hbm_bytes_per_sweep"] * sweeps
 
 
+def _line(metric, value, unit, steps, warmup, ms, higher, dtype, config, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+           "ms_per_step": ms, "higher_is_better": higher, "scaling": "weak", "vs_baseline": None,
+           "dtype": dtype, "data": "synthetic", "config": config}
+    out.update(extra)
+    return out
+
+
+def _timed(fn, steps, warmup):
+    import torch
+    r = None
+    for _ in range(warmup):
+        r = fn()
+    torch.cuda.synchronize()
+    rs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rs.append(fn())
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, rs
+
+
+def bench_bf16(args):
+    """Wide 2000 x 200,000 system: time to a true relative residual of 1e-6."""
+    import torch
+    from paper_2104_12570_amd import hpscd
+    from workloads import gen
+    s = gen.wide()
+    X32 = torch.from_numpy(s.Xt).cuda()
+    y = torch.from_numpy(s.y).cuda()
+    Xb = hpscd.convert_bf16(X32)
+    tol, check, refresh = 1e-6, 1024, 16384
+    kw = dict(max_sweeps=3, stop=hpscd.STOP_REL_RESID, tol=tol, check_cols=check, block=8, want_hist=False)
+    ms_b, rb = _timed(lambda: hpscd.solve_bf16(Xb, X32, y, refresh_cols=refresh, **kw), args.steps, args.warmup)
+    ms_f, rf = _timed(lambda: hpscd.solve(X32, y, **kw), args.steps, args.warmup)
+    ib, jf = rb[-1].info, rf[-1].info
+    log("bf16:", ib)
+    log("fp32:", jf)
+    cols = ib["cols_done"]
+    alg = cols * s.m * 2.0
+    sweep_ms = float(np.mean([r.info["sweep_ms"] for r in rb]))
+    achieved = alg / (sweep_ms / 1e3) / 1e9
+    return _line("time_to_rel_resid_1e-6", ms_b, "ms", args.steps, args.warmup, ms_b, False, "bf16-storage/f32",
+                 {"workload": f"wide {s.m}x{s.n}, X bf16 + FP32 copy, refresh every {refresh} columns, "
+                              f"stop when ||y - X a||/||y|| < {tol:g} (checked every {check} columns, "
+                              "confirmed on the refreshed residual)",
+                  "m": s.m, "n": s.n, "bf16": {"ms": ms_b, "cols": cols, "refreshes": ib["refreshes"],
+                                               "true_rel_resid": ib["final_rel_resid"], "converged": ib["converged"]},
+                  "fp32_plain": {"ms": ms_f, "cols": jf["cols_done"], "true_rel_resid": jf["final_rel_resid"],
+                                 "stopped_on_running_resid": jf["converged"],
+                                 "reaches_tol": bool(jf["final_rel_resid"] < tol)},
+                  "speedup_vs_fp32": ms_f / ms_b},
+                 roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "k_sweep (one workgroup, bf16)", "alg_bytes_per_launch": alg,
+                           "launch_ms": sweep_ms,
+                           "note": "one column step depends on the previous one; a single workgroup "
+                                   "carries the chain, so the sweep is latency-bound"})
+
+
+def bench_batched(args):
+    """4096 uneven tall systems: one persistent launch vs one call per system."""
+    import torch
+    from paper_2104_12570_amd import hpscd
+    from workloads import gen
+    t0 = time.perf_counter()
+    b = gen.batch()
+    log(f"generated batch of {b.count} in {time.perf_counter() - t0:.1f}s")
+    Xp = torch.from_numpy(b.Xpool).cuda()
+    yp = torch.from_numpy(b.ypool).cuda()
+    kw = dict(max_sweeps=100, stop=hpscd.STOP_REL_CHANGE, tol=1e-6)
+    hpscd.autotune_batched(Xp, yp, b.table, **kw)
+    ms, rs = _timed(lambda: hpscd.solve_batched(Xp, yp, b.table, **kw), args.steps, args.warmup)
+    r = rs[-1]
+    m, n = b.table[:, 0], b.table[:, 1]
+    updates = float(np.sum(r.sweeps * n))
+    alg = float(np.sum(r.sweeps * m * n)) * 4.0
+    sweep_ms = float(np.mean([x.info["sweep_ms"] for x in rs]))
+    achieved = alg / (sweep_ms / 1e3) / 1e9
+    # one call per system (same stop rule), timed once after one warm pass
+    views = [(Xp[b.table[i, 2]: b.table[i, 2] + n[i] * b.table[i, 3]].view(int(n[i]), int(b.table[i, 3])),
+              yp[b.table[i, 4]: b.table[i, 4] + m[i]]) for i in range(b.count)]
+    for Xi, yi in views[:64]:
+        hpscd.solve(Xi, yi, want_hist=False, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single_updates = 0
+    for Xi, yi in views:
+        single_updates += hpscd.solve(Xi, yi, want_hist=False, **kw).info["sweeps_done"] * Xi.shape[0]
+    torch.cuda.synchronize()
+    single_ms = (time.perf_counter() - t0) * 1e3
+    log("batched:", r.info)
+    return _line("coord_updates_per_s", updates / (ms / 1e3), "coord_updates/s", args.steps, args.warmup, ms, True,
+                 "f32",
+                 {"workload": f"batched: {b.count} tall systems, m log-uniform [256, 8192], n log-uniform [8, 128], "
+                              "sweeps until rel. change of ||e|| < 1e-6",
+                  "systems": b.count, "sum_mn": int(np.sum(m * n)), "sweeps_mean": float(np.mean(r.sweeps)),
+                  "block": r.info["block_used"], "per_system_calls": {
+                      "ms": single_ms, "coord_updates_per_s": single_updates / (single_ms / 1e3)},
+                  "speedup_vs_per_system_calls": single_ms / ms},
+                 roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batched",
+                           "alg_bytes_per_launch": alg, "launch_ms": sweep_ms})
+
+
+def bench_warmstart(args):
+    """Radial-basis family: learned warm start vs zero start on held-out systems."""
+    import torch
+    from paper_2104_12570_amd import hpscd, warmstart
+    from workloads import gen
+    from workloads.rbf_torch import rbf_pool
+    K, ntr, nte = 100, args.ws_train, 2000
+    t0 = time.perf_counter()
+    Ptr, Ttr = gen.rbf_params(5, ntr)
+    Pte, Tte = gen.rbf_params(6, nte)
+    Xtr, ytr, tabtr = rbf_pool(Ptr, Ttr, device="cuda")
+    del Ttr
+    torch.cuda.synchronize()
+    log(f"built {ntr} training systems in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    lab = warmstart.label(Xtr, ytr, tabtr, K)
+    torch.cuda.synchronize()
+    label_s = time.perf_counter() - t0
+    del Xtr, ytr
+    ws = warmstart.WarmStart(13, 64, seed=0)
+    feats = torch.from_numpy(gen.rbf_features(Ptr)).cuda()
+    t0 = time.perf_counter()
+    hist = ws.fit(feats, lab.a, epochs=args.ws_epochs, batch=512, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"labels {label_s:.2f}s, training {train_s:.1f}s, loss {hist[0]:.3f} -> {hist[-1]:.4f}")
+    Xte, yte, tabte = rbf_pool(Pte, Tte, device="cuda")
+    ref = warmstart.label(Xte, yte, tabte, K)
+    fte = torch.from_numpy(gen.rbf_features(Pte)).cuda()
+    tols = ref.tau
+
+    def warm():
+        a0 = ws.predict(fte)
+        return warmstart.solve_from(Xte, yte, tabte, a0, tols=tols, max_sweeps=K)
+
+    def zero():
+        return hpscd.solve_batched(Xte, yte, tabte, max_sweeps=K)
+
+    ms_w, rw = _timed(warm, args.steps, args.warmup)
+    ms_z, rz = _timed(zero, args.steps, args.warmup)
+    w, z = rw[-1], rz[-1]
+    a0 = ws.predict(fte)
+    err = ((a0 - ref.a).norm(dim=1) / ref.a.norm(dim=1)).cpu().numpy()
+    reached = w.final_rel_resid <= tols * (1 + 1e-3)
+    budgets = {}
+    for bgt in (10, 100):
+        rzb = hpscd.solve_batched(Xte, yte, tabte, max_sweeps=bgt)
+        rwb = hpscd.solve_batched(Xte, yte, tabte, a0.reshape(-1).contiguous(), max_sweeps=bgt)
+        budgets[str(bgt)] = {"zero_median_rel_resid": float(np.median(rzb.final_rel_resid)),
+                             "warm_median_rel_resid": float(np.median(rwb.final_rel_resid))}
+    return _line("time_to_target_residual", ms_w, "ms", args.steps, args.warmup, ms_w, False, "f32",
+                 {"workload": f"rbf family m=4096 n=64: {nte} held-out systems solved to the residual "
+                              f"that {K} sweeps from zero reach (per system), from the network's a0; "
+                              "time includes the network forward and the a0 residual pass",
+                  "train_systems": ntr, "label_sweeps": K, "label_s": label_s, "train_s": train_s,
+                  "epochs": args.ws_epochs, "net": "13-256-256-64 GELU",
+                  "zero_start_ms": ms_z, "speedup_vs_zero_start": ms_z / ms_w,
+                  "sweeps_mean_warm": float(np.mean(w.sweeps)), "sweeps_median_warm": float(np.median(w.sweeps)),
+                  "sweeps_zero": K, "reached_target_frac": float(np.mean(reached)),
+                  "a0_rel_err_median": float(np.median(err)), "tau_median": float(np.median(tols)),
+                  "equal_budget": budgets},
+                 roofline=None)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--form", choices=["plain", "bf16", "batched", "warmstart"], default="plain")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--m", type=int, default=1_000_000)
@@ -76,12 +261,19 @@ def main():
     ap.add_argument("--fixed-sweeps", type=int, default=0, help="run exactly this many sweeps (no stop test)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ws-train", type=int, default=50_000, help="warmstart: training systems")
+    ap.add_argument("--ws-epochs", type=int, default=400, help="warmstart: training epochs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+
+    if args.form != "plain":
+        out = {"bf16": bench_bf16, "batched": bench_batched, "warmstart": bench_warmstart}[args.form](args)
+        print(json.dumps(out), flush=True)
+        return
 
     import torch
     from paper_2104_12570_amd import hpscd

@@ -71,7 +71,9 @@ typedef struct {
   int32_t block;        /* columns per reduction round (1, 2, 4 or 8); 0 = library choice */
   int32_t flags;        /* HPSCD_F_* */
   int32_t team_threads; /* threads per workgroup; 0 = library choice */
-  int32_t depth;        /* blocks held in the prefetch ring (2 or 3); 0 = library choice */
+  int32_t depth;        /* kernel kind; 0 = library choice.  2, 3: prefetch ring of 2 or 3 blocks;
+                           4: pipelined grid kernel, or a 4-block ring for one workgroup;
+                           12, 13: grid kernel with a dedicated reduction wave, ring of 2 or 3 */
 } hpscd_opts;
 
 typedef struct {

@@ -112,7 +112,10 @@ def solve(Xt, y, m=None, a0=None, max_sweeps=1, tol=0.0, stop=STOP_NONE,
     y: (m,) right-hand side.  a0: optional initial guess.
     on_step(j, e_before, e_after, da, g, d): optional per-step hook.
     Xt_refresh / refresh_cols: when both are given, every ``refresh_cols``
-    column steps e is recomputed as y - X_refresh·a (FP64).
+    column steps e is recomputed as y - X_refresh·a (FP64); under
+    STOP_REL_RESID a stop that the running residual signals is confirmed on
+    a recomputed residual (counted as a refresh) and the sweeps go on from
+    that residual when it does not pass.
     Returns an ``OracleResult``.
     """
     n = Xt.shape[0]
@@ -128,7 +131,20 @@ def solve(Xt, y, m=None, a0=None, max_sweeps=1, tol=0.0, stop=STOP_NONE,
         if x @ x == 0.0:
             zero_cols += 1
     res = OracleResult(a, e, hist, 0, 0, False, zero_cols)
-    if stop == STOP_REL_RESID and (hist[0] == 0.0 or hist[0] < tol * ynorm):
+    confirm = stop == STOP_REL_RESID and bool(refresh_cols) and Xt_refresh is not None
+
+    def passes(nrm):
+        return nrm == 0.0 or nrm < tol * ynorm
+
+    def confirmed():
+        # reduced-precision form: a stop signalled by the running residual
+        # holds only if the residual recomputed from Xt_refresh passes too
+        nonlocal e
+        e = residual(Xt_refresh, y, m, a)
+        res.refreshes += 1
+        return passes(float(np.linalg.norm(e)))
+
+    if stop == STOP_REL_RESID and passes(hist[0]) and (not confirm or confirmed()):
         res.converged = True
         return res
     if stop != STOP_NONE and hist[0] == 0.0:
@@ -155,14 +171,16 @@ def solve(Xt, y, m=None, a0=None, max_sweeps=1, tol=0.0, stop=STOP_NONE,
             if (j < n - 1 and check_cols and stop == STOP_REL_RESID
                     and cols % check_cols == 0):
                 nrm = float(np.linalg.norm(e))
-                if nrm == 0.0 or nrm < tol * ynorm:
+                if passes(nrm) and (not confirm or confirmed()):
                     res.a, res.e, res.cols, res.sweeps, res.converged = a, e, cols, s - 1, True
                     res.extra["stop_norm"] = nrm
                     return res
         hist.append(float(np.linalg.norm(e)))
         if stop != STOP_NONE and _sweep_stop(stop, tol, hist, ynorm):
-            res.a, res.e, res.cols, res.sweeps, res.converged = a, e, cols, s, True
-            return res
+            if not confirm or confirmed():
+                res.a, res.e, res.cols, res.sweeps, res.converged = a, e, cols, s, True
+                return res
+            hist[-1] = float(np.linalg.norm(e))
     res.a, res.e, res.cols, res.sweeps = a, e, cols, max_sweeps
     return res
 

@@ -176,11 +176,11 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
   // kind (4) tests the stop rule only at sweep ends, so it is only used when
   // asked for and the caller does not need checks inside a sweep.
   std::vector<int> kinds;
-  if (o->depth == 4 && o->check_cols > 0 && o->stop == HPSCD_STOP_REL_RESID)
+  if (grid && o->depth == 4 && o->check_cols > 0 && o->stop == HPSCD_STOP_REL_RESID)
     return fail(HPSCD_EINVAL, "the pipelined kernel (depth 4) tests the stop rule only at sweep ends");
   if (o->depth != 0) kinds = {o->depth};
   else if (grid) kinds = {2, 3};  // measured fastest on the 1M x 256 system; 4, 12, 13 are selectable
-  else kinds = {3, 2};
+  else kinds = {4, 3, 2};         // one workgroup: the deepest ring hides the most load latency
   auto kind_of = [&](int T, int R, int b) {
     for (int k : kinds)
       if (sweep_variant_exists(T, R, b, bf16, grid, k)) return k;
@@ -303,11 +303,41 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   const int64_t seg = (o->refresh_cols > 0) ? std::max<int64_t>(1, o->refresh_cols / B) : total;
   const bool coop = pl.grid && !(o->flags & HPSCD_F_NO_COOP);
   int refreshes = 0;
-  for (int64_t kb = 0; kb < total; kb += seg) {
-    A.e0 = (kb == 0) ? e0 : c->eo.as<float>();
+  // bf16 form with the relative-residual rule: the running residual comes
+  // from the bfloat16 columns, so a stop it signals is confirmed on the
+  // residual recomputed from X32 (FP64 sums); if that one is not yet under
+  // the tolerance, the sweeps resume where they stopped.
+  const bool confirm = bf16 && o->refresh_cols > 0 && o->stop == HPSCD_STOP_REL_RESID;
+  CtlBlock* hcb = reinterpret_cast<CtlBlock*>(c->host);
+  bool resumed = false;
+  for (int64_t kb = 0; kb < total;) {
+    A.e0 = (kb == 0 && !resumed) ? e0 : c->eo.as<float>();
     A.blk_begin = kb;
-    A.blk_end = std::min(total, kb + seg);
+    A.blk_end = std::min(total, (kb / seg + 1) * seg);  // refreshes stay on multiples of refresh_cols
     HIP_TRY(launch_sweep(pl.T, pl.R, B, bf16, pl.grid, pl.D, A, st, coop));
+    if (confirm) {
+      HIP_TRY(hipMemcpyAsync(hcb, cb, sizeof(CtlBlock), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (hcb->ctl[CTL_DONE]) {
+        if (!hcb->ctl[CTL_CONVERGED] || hcb->ctl[CTL_ERR] || hcb->ctl[CTL_NONFINITE]) break;
+        const int64_t cs = hcb->ctl64[C64_COLS];
+        const int64_t touched = a0 ? n : std::min(n, cs);
+        HIP_TRY(launch_residual(X32, ldx32, m, touched, y, c->a64.as<double>(), nullptr, c->eo.as<float>(), fnorm2,
+                                partial, partial_cap, nullptr, st));
+        ++refreshes;
+        HIP_TRY(hipMemcpyAsync(hcb, cb, sizeof(CtlBlock), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const double ynorm = std::sqrt(hcb->ynorm2);
+        if (hcb->fnorm2 == 0.0 || std::sqrt(hcb->fnorm2) < o->tol * ynorm) break;
+        // not yet: clear the stop and resume at the block where it fired
+        HIP_TRY(launch_fill_i32(&ctl[CTL_CONVERGED], 1, 0, st));
+        HIP_TRY(launch_fill_i32(&ctl[CTL_DONE], 1, 0, st));
+        if (pl.grid) HIP_TRY(launch_fill_u64(c->slots.as<uint64_t>(), 4 * (int64_t)(B + 1) * pl.P, 0, st));
+        kb = (cs / n) * nb + (cs % n) / B;
+        resumed = true;
+        continue;
+      }
+    }
     if (o->refresh_cols > 0 && A.blk_end < total) {
       const int64_t cols = (A.blk_end / nb) * n + (A.blk_end % nb) * B;
       const int64_t touched = a0 ? n : std::min(n, cols);
@@ -315,6 +345,7 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
                               partial, partial_cap, &ctl[CTL_DONE], st));
       ++refreshes;
     }
+    kb = A.blk_end;
   }
   HIP_TRY(hipEventRecord(c->ev[2], st));
   HIP_TRY(launch_a_out(c->a64.as<double>(), a_out, n, st));

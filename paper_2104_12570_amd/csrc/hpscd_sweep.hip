@@ -76,7 +76,7 @@ __device__ inline void forward_substitute(const double (&tot)[B + 1], const Coef
 // --------------------------------------------------------------------------
 template <class S, int T, int R, int B, bool GRID, int D>
 __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
-  static_assert(D == 2 || D == 3, "prefetch ring of 2 or 3 blocks");
+  static_assert(D == 2 || D == 3 || (D == 4 && !GRID), "prefetch ring of 2 or 3 blocks (4 for one workgroup)");
   using raw = typename S::raw_t;
   constexpr int VEC = S::VEC;
   constexpr int NW = T / WAVE;
@@ -114,8 +114,8 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
   const int64_t col_bytes = A.ldx * (int64_t)(16 / VEC);
   // Ring of D register buffers: the current block and the next D-1 blocks,
   // whose loads are in flight while the current block is reduced.
-  raw x0[B][R], x1[B][R], x2[D == 3 ? B : 1][R];
-  Coef<B> c0, c1, c2;
+  raw x0[B][R], x1[B][R], x2[D >= 3 ? B : 1][R], x3[D >= 4 ? B : 1][R];
+  Coef<B> c0, c1, c2, c3;
 
   // Columns of one block are read through a buffer resource based at the
   // block's first column: one 32-bit lane offset per chunk, one scalar offset
@@ -349,8 +349,13 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
   };
 
   if (nblocks > 0) load_block(x0, c0, bi);
-  if constexpr (D == 3) {
+  if constexpr (D >= 3) {
     if (nblocks > 1) load_block(x1, c1, bi + 1 == nb ? 0 : bi + 1);
+  }
+  if constexpr (D >= 4) {
+    int b2 = bi + 2;
+    while (b2 >= nb) b2 -= nb;
+    if (nblocks > 2) load_block(x2, c2, b2);
   }
   __syncthreads();
   for (int64_t k = 0; k < nblocks;) {
@@ -359,12 +364,21 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
       if (++k >= nblocks) break;
       if (step(x1, x0, c1, c0, k + 1 < nblocks)) break;
       ++k;
-    } else {
+    } else if constexpr (D == 3) {
       if (step(x0, x2, c0, c2, k + 2 < nblocks)) break;
       if (++k >= nblocks) break;
       if (step(x1, x0, c1, c0, k + 2 < nblocks)) break;
       if (++k >= nblocks) break;
       if (step(x2, x1, c2, c1, k + 2 < nblocks)) break;
+      ++k;
+    } else {
+      if (step(x0, x3, c0, c3, k + 3 < nblocks)) break;
+      if (++k >= nblocks) break;
+      if (step(x1, x0, c1, c0, k + 3 < nblocks)) break;
+      if (++k >= nblocks) break;
+      if (step(x2, x1, c2, c1, k + 3 < nblocks)) break;
+      if (++k >= nblocks) break;
+      if (step(x3, x2, c3, c2, k + 3 < nblocks)) break;
       ++k;
     }
   }
@@ -1201,7 +1215,9 @@ __global__ void __launch_bounds__(BT) k_batched(BatchArgs A) {
   X_(F32, 256, 4, 8, false, 2)                                                                 \
   X_(BF16, 1024, 1, 1, true, 2) X_(BF16, 1024, 1, 8, true, 2)                                 \
   X_(BF16, 256, 1, 1, false, 2) X_(BF16, 256, 1, 4, false, 2) X_(BF16, 256, 1, 8, false, 2)   \
-  X_(BF16, 256, 2, 1, false, 2) X_(BF16, 256, 2, 4, false, 2) X_(BF16, 256, 2, 8, false, 2)
+  X_(BF16, 256, 2, 1, false, 2) X_(BF16, 256, 2, 4, false, 2) X_(BF16, 256, 2, 8, false, 2)   \
+  X_(F32, 256, 2, 8, false, 3) X_(F32, 256, 2, 8, false, 4) X_(F32, 256, 2, 4, false, 4)       \
+  X_(BF16, 256, 1, 8, false, 3) X_(BF16, 256, 1, 8, false, 4) X_(BF16, 256, 1, 4, false, 4)
 
 #define HPSCD_PIPE_VARIANTS(X_)                                                   \
   X_(F32, 1024, 1, 2) X_(F32, 512, 2, 2) X_(F32, 512, 2, 4) X_(F32, 256, 4, 4)    \

@@ -253,17 +253,37 @@ def residual_f64(Xt, y, a, want_e=False):
     return nrm.value, e
 
 
+_SYS_DTYPE = np.dtype([("m", "<i8"), ("n", "<i8"), ("x_off", "<i8"), ("ldx", "<i8"), ("y_off", "<i8"),
+                       ("a_off", "<i8"), ("tol", "<f8")])
+
+
+class _SysTable:
+    """hpscd_sys rows in a NumPy buffer, passed to C by address."""
+
+    def __init__(self, rec):
+        self.rec = rec
+
+    @property
+    def _as_parameter_(self):
+        return ctypes.cast(self.rec.ctypes.data, ctypes.POINTER(Sys))
+
+    def __getitem__(self, i):
+        return Sys(*[v.item() for v in self.rec[i]])
+
+
 def _sys_array(table, tols=None):
-    """ctypes array of hpscd_sys from rows (m, n, x_off, ldx, y_off, a_off)
-    and optional per-system tolerances (0 = the call's tol)."""
+    """hpscd_sys table from rows (m, n, x_off, ldx, y_off, a_off) and optional
+    per-system tolerances (0 = the call's tol)."""
+    assert ctypes.sizeof(Sys) == _SYS_DTYPE.itemsize
     table = np.asarray(table, dtype=np.int64).reshape(-1, 6)
     tols = np.zeros(len(table)) if tols is None else np.asarray(tols, dtype=np.float64).reshape(-1)
     if len(tols) != len(table):
         raise ValueError("tols needs one entry per system")
-    arr = (Sys * len(table))()
-    for i, row in enumerate(table):
-        arr[i] = Sys(*[int(v) for v in row], float(tols[i]))
-    return arr
+    rec = np.empty(len(table), dtype=_SYS_DTYPE)
+    for k, name in enumerate(_SYS_DTYPE.names[:6]):
+        rec[name] = table[:, k]
+    rec["tol"] = tols
+    return _SysTable(rec)
 
 
 @dataclass

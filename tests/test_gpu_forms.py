@@ -137,3 +137,31 @@ def test_bf16_pipelined_refresh_mid_sweep(lib):
     assert r.info["refreshes"] == ref.refreshes == 8
     assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5, r.info
     assert np.all(np.abs(np.asarray(r.hist) - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0])
+
+
+@pytest.mark.parametrize("size", ["mid", "full"])
+def test_bf16_time_to_tolerance_is_confirmed(lib, size):
+    """Relative-residual stop of the storage form on the wide system: the
+    stop is confirmed on the residual recomputed from FP32 X, so the FP64
+    final check is under tol; stop point and refresh count follow the oracle.
+    "full" is the 2000 x 200,000 system in the configuration the benchmark
+    times (check every 1024 columns, refresh every 16384)."""
+    if size == "mid":
+        s = gen.wide(m=2000, n=20_000, seed=5)
+        tol, check, refresh = 1e-6, 512, 2048
+    else:
+        s = gen.wide()
+        tol, check, refresh = 1e-6, 1024, 16384
+    say("bf16 confirm", size)
+    X32 = dev(s.Xt)
+    Xb = lib.convert_bf16(X32)
+    r = lib.solve_bf16(Xb, X32, dev(s.y), max_sweeps=3, stop=lib.STOP_REL_RESID, tol=tol, check_cols=check,
+                       refresh_cols=refresh, block=8)
+    ref = oracle.solve_bf16_refresh(s.Xt, s.y, s.m, max_sweeps=3, stop=oracle.STOP_REL_RESID, tol=tol,
+                                    check_cols=check, refresh_cols=refresh)
+    assert ref.converged and r.info["converged"] == 1
+    assert r.info["final_rel_resid"] < tol
+    assert abs(r.info["cols_done"] - ref.cols) <= check
+    assert abs(r.info["refreshes"] - ref.refreshes) <= 1
+    if r.info["cols_done"] == ref.cols:
+        assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5

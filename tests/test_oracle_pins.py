@@ -310,6 +310,23 @@ def test_bf16_form_refresh_restores_accuracy():
     np.testing.assert_allclose(r_yes.e, oracle.residual(X32, s.y, s.m, r_yes.a), atol=1e-12)
 
 
+def test_bf16_relative_residual_stop_is_confirmed():
+    """The relative-residual rule is a statement about the true residual
+    y - X·a.  In the storage form the running residual drifts from it (below
+    the bfloat16 floor it is meaningless), so a stop it signals must be
+    confirmed on the recomputed residual: every converged result then has a
+    true relative residual under tol, which the unconfirmed rule misses."""
+    s = gen.wide(m=200, n=2000, seed=5)
+    X32, tol = s.Xt, 1e-5
+    kw = dict(max_sweeps=60, stop=oracle.STOP_REL_RESID, tol=tol, check_cols=100)
+    bad = oracle.solve(ho.bf16_round(X32), s.y, s.m, **kw)          # running residual only
+    assert bad.converged and oracle.final_rel_resid(X32, s.y, s.m, bad.a) > 1e-4
+    r = oracle.solve_bf16_refresh(X32, s.y, s.m, refresh_cols=1000, **kw)
+    assert r.converged
+    assert oracle.final_rel_resid(X32, s.y, s.m, r.a) < tol
+    assert r.cols % 100 == 0 and r.refreshes >= r.cols // 1000 + 1
+
+
 def test_batch_equals_single():
     b = gen.batch(seed=4, count=6, m_lo=64, m_hi=300, n_lo=3, n_hi=20)
     rs = oracle.solve_batch(b, max_sweeps=5)
