@@ -20,8 +20,9 @@ Other forms (``--form``), each printing one JSON line of its own:
                 residual of 1e-6 (stop confirmed on the refreshed residual),
                 beside the plain FP32 solve under the same rule;
 * ``batched``   4096 independent tall systems (m log-uniform in [256, 8192],
-                n in [8, 128]) in one autotuned persistent launch, beside one
-                solve call per system;
+                n in [8, 128]) in one autotuned persistent launch, recorded
+                once as a HIP graph and replayed, beside one solve call per
+                system;
 * ``warmstart`` the radial-basis family (m = 4096, n = 64): labels from 100
                 sweeps on 50,000 training systems, network training, then
                 2,000 held-out systems solved from the predicted a0 to the
@@ -152,12 +153,22 @@ def bench_batched(args):
     yp = torch.from_numpy(b.ypool).cuda()
     kw = dict(max_sweeps=100, stop=hpscd.STOP_REL_CHANGE, tol=1e-6)
     hpscd.autotune_batched(Xp, yp, b.table, **kw)
-    ms, rs = _timed(lambda: hpscd.solve_batched(Xp, yp, b.table, **kw), args.steps, args.warmup)
+    # device time of the kernels from one eager call (HIP events)
+    eager = hpscd.solve_batched(Xp, yp, b.table, **kw)
+    plan = hpscd.BatchPlan(Xp, yp, b.table, **kw)
+
+    def step():
+        plan.launch()
+        return plan.results()
+
+    ms, rs = _timed(step, args.steps, args.warmup)
+    ms_eager, _ = _timed(lambda: hpscd.solve_batched(Xp, yp, b.table, **kw), args.steps, 1)
     r = rs[-1]
+    assert torch.equal(r.a, eager.a)
     m, n = b.table[:, 0], b.table[:, 1]
     updates = float(np.sum(r.sweeps * n))
     alg = float(np.sum(r.sweeps * m * n)) * 4.0
-    sweep_ms = float(np.mean([x.info["sweep_ms"] for x in rs]))
+    sweep_ms = eager.info["sweep_ms"]
     achieved = alg / (sweep_ms / 1e3) / 1e9
     # one call per system (same stop rule), timed once after one warm pass
     views = [(Xp[b.table[i, 2]: b.table[i, 2] + n[i] * b.table[i, 3]].view(int(n[i]), int(b.table[i, 3])),
@@ -171,13 +182,14 @@ def bench_batched(args):
         single_updates += hpscd.solve(Xi, yi, want_hist=False, **kw).info["sweeps_done"] * Xi.shape[0]
     torch.cuda.synchronize()
     single_ms = (time.perf_counter() - t0) * 1e3
-    log("batched:", r.info)
+    log("batched:", eager.info)
     return _line("coord_updates_per_s", updates / (ms / 1e3), "coord_updates/s", args.steps, args.warmup, ms, True,
                  "f32",
                  {"workload": f"batched: {b.count} tall systems, m log-uniform [256, 8192], n log-uniform [8, 128], "
                               "sweeps until rel. change of ||e|| < 1e-6",
                   "systems": b.count, "sum_mn": int(np.sum(m * n)), "sweeps_mean": float(np.mean(r.sweeps)),
-                  "block": r.info["block_used"], "per_system_calls": {
+                  "block": eager.info["block_used"], "graph_replay": True, "eager_call_ms": ms_eager,
+                  "per_system_calls": {
                       "ms": single_ms, "coord_updates_per_s": single_updates / (single_ms / 1e3)},
                   "speedup_vs_per_system_calls": single_ms / ms},
                  roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -216,12 +228,21 @@ def bench_warmstart(args):
     fte = torch.from_numpy(gen.rbf_features(Pte)).cuda()
     tols = ref.tau
 
+    # Both solves are recorded once as HIP graphs; a step of the warm start is
+    # the network forward (written straight into the plan's a0 pool) plus one
+    # replay, a step of the zero start one replay.
+    a0buf = torch.empty(nte * 64, dtype=torch.float32, device="cuda")
+    plan_w = hpscd.BatchPlan(Xte, yte, tabte, a0pool=a0buf, max_sweeps=K, stop=hpscd.STOP_REL_RESID, tols=tols)
+    plan_z = hpscd.BatchPlan(Xte, yte, tabte, max_sweeps=K)
+
     def warm():
-        a0 = ws.predict(fte)
-        return warmstart.solve_from(Xte, yte, tabte, a0, tols=tols, max_sweeps=K)
+        ws.predict(fte, out=a0buf)
+        plan_w.launch()
+        return plan_w.results()
 
     def zero():
-        return hpscd.solve_batched(Xte, yte, tabte, max_sweeps=K)
+        plan_z.launch()
+        return plan_z.results()
 
     ms_w, rw = _timed(warm, args.steps, args.warmup)
     ms_z, rz = _timed(zero, args.steps, args.warmup)

@@ -153,10 +153,35 @@ hpscd_status hpscd_solve_batched_f32(hpscd_ctx* ctx, int32_t count, const hpscd_
                                      double* hist, int32_t* sweeps_done, int32_t* converged,
                                      double* final_rel_resid, hpscd_info* info, void* stream);
 
-/* Time the batched kernel's variants on this batch and remember the fastest
- * for batches of the same shape (kept in the context). */
+/* Time the batched kernel's variants on this batch (block size 1, 2 or 4;
+ * systems that fit one wave packed four to a workgroup, or one workgroup per
+ * system) and remember the fastest for batches of the same shape (kept in the
+ * context). */
 hpscd_status hpscd_autotune_batched(hpscd_ctx* ctx, int32_t count, const hpscd_sys* sys, const float* Xpool,
                                     const float* ypool, const hpscd_opts* opts, float* apool, void* stream);
+
+/* Recorded batched solve.  hpscd_batched_plan_create validates and plans the
+ * batch once (block size and work split from hpscd_autotune_batched when it
+ * was run on a batch of this shape), uploads the system table into the
+ * plan's own device workspace, and records the whole solve (initial
+ * residuals, column statistics, the persistent sweep kernel, the output of a
+ * and the FP64 check) as a HIP graph.  The pools are bound by address: their
+ * contents (X, y, a0) may change between launches, their addresses may not.
+ * hpscd_batched_plan_launch queues one replay on `stream` and returns without
+ * waiting; hpscd_batched_plan_results waits for `stream` and returns the
+ * per-system results of the last replay (arguments as in
+ * hpscd_solve_batched_f32; info->sweep_ms and total_ms are NaN).  A plan
+ * belongs to its context (same thread rules); replays of one plan must not
+ * overlap.  The host staging buffer of the context is used by results. */
+typedef struct hpscd_batch_plan hpscd_batch_plan;
+
+hpscd_status hpscd_batched_plan_create(hpscd_ctx* ctx, int32_t count, const hpscd_sys* sys, const float* Xpool,
+                                       const float* ypool, const float* a0pool, const hpscd_opts* opts,
+                                       float* apool, hpscd_batch_plan** plan);
+hpscd_status hpscd_batched_plan_launch(hpscd_batch_plan* plan, void* stream);
+hpscd_status hpscd_batched_plan_results(hpscd_batch_plan* plan, double* hist, int32_t* sweeps_done,
+                                        int32_t* converged, double* final_rel_resid, hpscd_info* info, void* stream);
+void hpscd_batched_plan_destroy(hpscd_batch_plan* plan);
 
 /* Ask a running solve on this context to stop at its next sweep boundary;
  * that solve returns HPSCD_EABORTED.  Safe to call from another thread. */

@@ -77,6 +77,15 @@ constexpr uint64_t kTimeoutTicks = 1000000000ull;  // 10 s of the 100 MHz clock
 
 struct Tuned {
   int B;
+  int64_t wave_max_m;  // systems with m <= this go four to a workgroup, one per wave
+};
+
+// Device workspace of one batched solve (the context's, or a plan's own).
+struct BatchWork {
+  DevBuf sys, items, blk, rdn, gram, a64, e0, hist, i32, f64;
+  void release() {
+    for (DevBuf* b : {&sys, &items, &blk, &rdn, &gram, &a64, &e0, &hist, &i32, &f64}) b->release();
+  }
 };
 
 }  // namespace
@@ -85,7 +94,7 @@ struct hpscd_ctx {
   int device = 0;
   int cus = 0;
   DevBuf ctlb, e0, eo, a64, rdn, gram, cross, partial, slots, hist;
-  DevBuf b_sys, b_items, b_blk, b_rdn, b_gram, b_a64, b_e0, b_hist, b_i32, b_f64;
+  BatchWork bw;
   void* host = nullptr;
   size_t host_cap = 0;
   hipStream_t side = nullptr;
@@ -432,10 +441,9 @@ void hpscd_destroy(hpscd_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  for (DevBuf* b : {&c->ctlb, &c->e0, &c->eo, &c->a64, &c->rdn, &c->gram, &c->cross, &c->partial, &c->slots, &c->hist,
-                    &c->b_sys, &c->b_items, &c->b_blk, &c->b_rdn, &c->b_gram, &c->b_a64, &c->b_e0, &c->b_hist,
-                    &c->b_i32, &c->b_f64})
+  for (DevBuf* b : {&c->ctlb, &c->e0, &c->eo, &c->a64, &c->rdn, &c->gram, &c->cross, &c->partial, &c->slots, &c->hist})
     b->release();
+  c->bw.release();
   if (c->host) (void)hipHostFree(c->host);
   for (auto& e : c->ev) if (e) (void)hipEventDestroy(e);
   if (c->side) (void)hipStreamDestroy(c->side);
@@ -554,7 +562,8 @@ hpscd_status validate_batch(int32_t count, const hpscd_sys* sys, const float* Xp
 // Work items in longest-processing-time order: systems that fit one wave are
 // grouped four to an item by decreasing size; larger systems get a whole
 // workgroup.  The queue hands items out in this order.
-void plan_batch(int32_t count, const hpscd_sys* sys, int B, int hist_len, double tol, BatchPlan* bp) {
+void plan_batch(int32_t count, const hpscd_sys* sys, int B, int64_t wave_max_m, int hist_len, double tol,
+                BatchPlan* bp) {
   bp->sd.resize(count);
   bp->blk_first.resize(count);
   int64_t g = 0, blk = 0;
@@ -572,7 +581,7 @@ void plan_batch(int32_t count, const hpscd_sys* sys, int B, int hist_len, double
   bp->rdn_size = g;
   bp->gram_size = g / B * (B * (B - 1) / 2);
   std::vector<int32_t> small, big;
-  const int64_t wave_rows = batched_rows_per_wave();
+  const int64_t wave_rows = std::min<int64_t>(wave_max_m, batched_rows_per_wave());
   for (int32_t i = 0; i < count; ++i) (sys[i].m <= wave_rows ? small : big).push_back(i);
   auto work = [&](int32_t i) { return (double)sys[i].m * (double)sys[i].n; };
   auto by_work = [&](int32_t a, int32_t b) { return work(a) > work(b); };
@@ -600,76 +609,93 @@ std::string batch_key(int32_t count, const hpscd_sys* sys) {
   return buf;
 }
 
-hpscd_status solve_batched(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, const float* Xpool, const float* ypool,
-                           const float* a0pool, const hpscd_opts* o, int B, float* apool, double* hist,
-                           int32_t* sweeps_done, int32_t* converged, double* final_rel, hpscd_info* info,
+// Sizes of the workspace regions of one batched solve.
+struct BatchLayout {
+  int32_t count = 0;
+  int hist_len = 0;
+  size_t sys_bytes = 0, item_bytes = 0, blk_bytes = 0;
+  size_t i32_n = 0;  // queue[4], ctl[12], sweeps[count], converged[count]
+  size_t f64_n = 0;  // ynorm2[count], fnorm2[count]
+};
+
+// Plan the batch, size the workspace, and upload the tables (waits for the
+// upload: the staging buffer is the context's pinned buffer).
+hpscd_status prepare_batch(hpscd_ctx* c, BatchWork& w, int32_t count, const hpscd_sys* sys, bool has_a0,
+                           const hpscd_opts* o, int B, int64_t wave_max_m, BatchPlan& bp, BatchLayout& L,
                            hipStream_t st) {
   HIP_TRY(hipSetDevice(c->device));
-  const int hist_len = o->max_sweeps + 1;
-  BatchPlan bp;
-  plan_batch(count, sys, B, hist_len, o->tol, &bp);
-  const int nitems = (int)bp.items.size();
+  L.count = count;
+  L.hist_len = o->max_sweeps + 1;
+  plan_batch(count, sys, B, wave_max_m, L.hist_len, o->tol, &bp);
+  L.sys_bytes = bp.sd.size() * sizeof(SysDesc);
+  L.item_bytes = bp.items.size() * sizeof(WorkItem);
+  L.blk_bytes = bp.blk_first.size() * sizeof(int64_t);
+  L.i32_n = 16 + 2 * (size_t)count;
+  L.f64_n = 2 * (size_t)count;
   hpscd_status rc;
-  const size_t sys_bytes = bp.sd.size() * sizeof(SysDesc);
-  const size_t item_bytes = bp.items.size() * sizeof(WorkItem);
-  const size_t blk_bytes = bp.blk_first.size() * sizeof(int64_t);
-  // i32 region: queue[4], sweeps[count], converged[count], ctl[8]
-  const size_t i32_n = 16 + 2 * (size_t)count;
-  // f64 region: ynorm2[count], fnorm2[count]
-  const size_t f64_n = 2 * (size_t)count;
-  if ((rc = ensure(c->b_sys, sys_bytes, "sys")) || (rc = ensure(c->b_items, item_bytes, "items")) ||
-      (rc = ensure(c->b_blk, blk_bytes, "blk")) || (rc = ensure(c->b_rdn, (size_t)bp.rdn_size * 8, "rdn")) ||
-      (rc = ensure(c->b_gram, (size_t)std::max<int64_t>(1, bp.gram_size) * 8, "gram")) ||
-      (rc = ensure(c->b_a64, (size_t)bp.a_size * 8, "a64")) ||
-      (rc = ensure(c->b_e0, a0pool ? (size_t)bp.y_size * 4 : 4, "e0")) ||
-      (rc = ensure(c->b_hist, (size_t)count * hist_len * 8, "hist")) || (rc = ensure(c->b_i32, i32_n * 4, "i32")) ||
-      (rc = ensure(c->b_f64, f64_n * 8, "f64")))
+  if ((rc = ensure(w.sys, L.sys_bytes, "sys")) || (rc = ensure(w.items, L.item_bytes, "items")) ||
+      (rc = ensure(w.blk, L.blk_bytes, "blk")) || (rc = ensure(w.rdn, (size_t)bp.rdn_size * 8, "rdn")) ||
+      (rc = ensure(w.gram, (size_t)std::max<int64_t>(1, bp.gram_size) * 8, "gram")) ||
+      (rc = ensure(w.a64, (size_t)bp.a_size * 8, "a64")) ||
+      (rc = ensure(w.e0, has_a0 ? (size_t)bp.y_size * 4 : 4, "e0")) ||
+      (rc = ensure(w.hist, (size_t)count * L.hist_len * 8, "hist")) || (rc = ensure(w.i32, L.i32_n * 4, "i32")) ||
+      (rc = ensure(w.f64, L.f64_n * 8, "f64")))
     return rc;
-  const size_t up = sys_bytes + item_bytes + blk_bytes;
-  const size_t down = i32_n * 4 + f64_n * 8 + (hist ? (size_t)count * hist_len * 8 : 0);
+  const size_t up = L.sys_bytes + L.item_bytes + L.blk_bytes;
+  const size_t down = L.i32_n * 4 + L.f64_n * 8 + (size_t)count * L.hist_len * 8;
   if ((rc = c->host_ensure(std::max(up, down) + 64))) return rc;
-  // The staging buffer is reused for the download only after the stream has
-  // drained the uploads (the synchronisation below).
   char* h = reinterpret_cast<char*>(c->host);
-  std::memcpy(h, bp.sd.data(), sys_bytes);
-  std::memcpy(h + sys_bytes, bp.items.data(), item_bytes);
-  std::memcpy(h + sys_bytes + item_bytes, bp.blk_first.data(), blk_bytes);
-  HIP_TRY(hipEventRecord(c->ev[0], st));
-  HIP_TRY(hipMemcpyAsync(c->b_sys.p, h, sys_bytes, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(c->b_items.p, h + sys_bytes, item_bytes, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(c->b_blk.p, h + sys_bytes + item_bytes, blk_bytes, hipMemcpyHostToDevice, st));
-  int32_t* i32 = c->b_i32.as<int32_t>();
+  HIP_TRY(hipStreamSynchronize(st));  // the staging buffer may still feed an earlier copy
+  std::memcpy(h, bp.sd.data(), L.sys_bytes);
+  std::memcpy(h + L.sys_bytes, bp.items.data(), L.item_bytes);
+  std::memcpy(h + L.sys_bytes + L.item_bytes, bp.blk_first.data(), L.blk_bytes);
+  HIP_TRY(hipMemcpyAsync(w.sys.p, h, L.sys_bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(w.items.p, h + L.sys_bytes, L.item_bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(w.blk.p, h + L.sys_bytes + L.item_bytes, L.blk_bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return HPSCD_OK;
+}
+
+// Queue the whole batched solve on `st`: kernels only (no copies, no
+// memsets, no host waits), so the sequence can be recorded into a HIP graph.
+// Events ev (four, or NULL) bracket setup, sweeps and output.
+hpscd_status enqueue_batch(hpscd_ctx* c, BatchWork& w, const BatchPlan& bp, const BatchLayout& L, const float* Xpool,
+                           const float* ypool, const float* a0pool, const hpscd_opts* o, int B, float* apool,
+                           hipEvent_t* ev, hipStream_t st) {
+  const int32_t count = L.count;
+  int32_t* i32 = w.i32.as<int32_t>();
   int32_t* queue = i32;
   int32_t* ctl = i32 + 4;
   int32_t* d_sweeps = i32 + 16;
   int32_t* d_conv = d_sweeps + count;
-  double* ynorm2 = c->b_f64.as<double>();
+  double* ynorm2 = w.f64.as<double>();
   double* fnorm2 = ynorm2 + count;
-  const SysDesc* dsys = c->b_sys.as<SysDesc>();
-  HIP_TRY(launch_fill_i32(i32, (int64_t)i32_n, 0, st));
-  HIP_TRY(launch_fill_f64(c->b_hist.as<double>(), (int64_t)count * hist_len, std::numeric_limits<double>::quiet_NaN(), st));
-  HIP_TRY(launch_a_init(c->b_a64.as<double>(), a0pool, bp.a_size, st));
+  const SysDesc* dsys = w.sys.as<SysDesc>();
+  if (ev) HIP_TRY(hipEventRecord(ev[0], st));
+  HIP_TRY(launch_fill_i32(i32, (int64_t)L.i32_n, 0, st));
+  HIP_TRY(launch_fill_f64(w.hist.as<double>(), (int64_t)count * L.hist_len, std::numeric_limits<double>::quiet_NaN(), st));
+  HIP_TRY(launch_a_init(w.a64.as<double>(), a0pool, bp.a_size, st));
   HIP_TRY(launch_residual_batched(Xpool, ypool, dsys, count, nullptr, nullptr, nullptr, ynorm2, st));
   const float* e0 = ypool;
   if (a0pool) {
-    HIP_TRY(launch_residual_batched(Xpool, ypool, dsys, count, nullptr, a0pool, c->b_e0.as<float>(), nullptr, st));
-    e0 = c->b_e0.as<float>();
+    HIP_TRY(launch_residual_batched(Xpool, ypool, dsys, count, nullptr, a0pool, w.e0.as<float>(), nullptr, st));
+    e0 = w.e0.as<float>();
   }
-  HIP_TRY(launch_colgram_batched(Xpool, dsys, count, bp.nblk, c->b_blk.as<int64_t>(), B, c->b_rdn.as<double>(),
-                                 c->b_gram.as<double>(), ctl + CTL_NONFINITE, st));
-  HIP_TRY(hipEventRecord(c->ev[1], st));
+  HIP_TRY(launch_colgram_batched(Xpool, dsys, count, bp.nblk, w.blk.as<int64_t>(), B, w.rdn.as<double>(),
+                                 w.gram.as<double>(), ctl + CTL_NONFINITE, st));
+  if (ev) HIP_TRY(hipEventRecord(ev[1], st));
   BatchArgs A{};
   A.Xpool = Xpool;
   A.ypool = ypool;
   A.sys = dsys;
-  A.items = c->b_items.as<WorkItem>();
-  A.nitems = nitems;
+  A.items = w.items.as<WorkItem>();
+  A.nitems = (int)bp.items.size();
   A.queue = queue;
-  A.rdn = c->b_rdn.as<double>();
-  A.gram = c->b_gram.as<double>();
+  A.rdn = w.rdn.as<double>();
+  A.gram = w.gram.as<double>();
   A.e0pool = e0;
-  A.a64pool = c->b_a64.as<double>();
-  A.hist = c->b_hist.as<double>();
+  A.a64pool = w.a64.as<double>();
+  A.hist = w.hist.as<double>();
   A.sweeps = d_sweeps;
   A.converged = d_conv;
   A.max_sweeps = o->max_sweeps;
@@ -678,21 +704,31 @@ hpscd_status solve_batched(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, co
   A.ynorm2 = ynorm2;
   const int per_cu = batched_max_blocks_per_cu(B);
   if (per_cu <= 0) return fail(HPSCD_EDEVICE, "batched kernel cannot be resident");
-  const int grid = std::max(1, std::min(nitems, per_cu * c->cus));
+  const int grid = std::max(1, std::min(A.nitems, per_cu * c->cus));
   HIP_TRY(launch_batched(B, A, grid, st));
-  HIP_TRY(hipEventRecord(c->ev[2], st));
-  HIP_TRY(launch_a_out_batched(c->b_a64.as<double>(), apool, dsys, count, st));
-  const bool check = !(o->flags & HPSCD_F_NO_FINAL_CHECK);
-  if (check) HIP_TRY(launch_residual_batched(Xpool, ypool, dsys, count, c->b_a64.as<double>(), nullptr, nullptr, fnorm2, st));
-  HIP_TRY(hipEventRecord(c->ev[3], st));
-  HIP_TRY(hipStreamSynchronize(st));  // uploads done; staging may be reused
-  HIP_TRY(hipMemcpyAsync(h, i32, i32_n * 4, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(h + i32_n * 4, ynorm2, f64_n * 8, hipMemcpyDeviceToHost, st));
+  if (ev) HIP_TRY(hipEventRecord(ev[2], st));
+  HIP_TRY(launch_a_out_batched(w.a64.as<double>(), apool, dsys, count, st));
+  if (!(o->flags & HPSCD_F_NO_FINAL_CHECK))
+    HIP_TRY(launch_residual_batched(Xpool, ypool, dsys, count, w.a64.as<double>(), nullptr, nullptr, fnorm2, st));
+  if (ev) HIP_TRY(hipEventRecord(ev[3], st));
+  return HPSCD_OK;
+}
+
+// Wait for `st` and copy the per-system results to the host.
+hpscd_status collect_batch(hpscd_ctx* c, BatchWork& w, const BatchLayout& L, const hpscd_sys* sys, bool check, int B,
+                           int grid, double* hist, int32_t* sweeps_done, int32_t* converged, double* final_rel,
+                           hpscd_info* info, hipEvent_t* ev, hipStream_t st) {
+  const int32_t count = L.count;
+  HIP_TRY(hipStreamSynchronize(st));  // the staging buffer is free once the stream has drained
+  char* h = reinterpret_cast<char*>(c->host);
+  HIP_TRY(hipMemcpyAsync(h, w.i32.p, L.i32_n * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(h + L.i32_n * 4, w.f64.p, L.f64_n * 8, hipMemcpyDeviceToHost, st));
   if (hist)
-    HIP_TRY(hipMemcpyAsync(h + i32_n * 4 + f64_n * 8, c->b_hist.p, (size_t)count * hist_len * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h + L.i32_n * 4 + L.f64_n * 8, w.hist.p, (size_t)count * L.hist_len * 8,
+                           hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const int32_t* hi = reinterpret_cast<const int32_t*>(h);
-  const double* hy = reinterpret_cast<const double*>(h + i32_n * 4);
+  const double* hy = reinterpret_cast<const double*>(h + L.i32_n * 4);
   if (sweeps_done) std::memcpy(sweeps_done, hi + 16, (size_t)count * 4);
   if (converged) std::memcpy(converged, hi + 16 + count, (size_t)count * 4);
   if (final_rel)
@@ -701,21 +737,23 @@ hpscd_status solve_batched(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, co
       final_rel[i] = check ? (yn > 0 ? std::sqrt(hy[count + i]) / yn : std::sqrt(hy[count + i]))
                            : std::numeric_limits<double>::quiet_NaN();
     }
-  if (hist) std::memcpy(hist, h + i32_n * 4 + f64_n * 8, (size_t)count * hist_len * 8);
+  if (hist) std::memcpy(hist, h + L.i32_n * 4 + L.f64_n * 8, (size_t)count * L.hist_len * 8);
   if (info) {
     std::memset(info, 0, sizeof *info);
-    int64_t swsum = 0, cvsum = 0;
-    for (int32_t i = 0; i < count; ++i) { swsum += hi[16 + i]; cvsum += hi[16 + count + i]; }
+    int64_t swsum = 0, cvsum = 0, cols = 0;
+    for (int32_t i = 0; i < count; ++i) {
+      swsum += hi[16 + i];
+      cvsum += hi[16 + count + i];
+      cols += (int64_t)hi[16 + i] * sys[i].n;
+    }
     info->sweeps_done = (int32_t)std::min<int64_t>(swsum, INT32_MAX);
     info->converged = (int32_t)cvsum;
-    int64_t cols = 0;
-    for (int32_t i = 0; i < count; ++i) cols += (int64_t)hi[16 + i] * sys[i].n;
     info->cols_done = cols;
     info->block_used = B;
     info->team_wgs = grid;
     info->team_threads = batched_threads();
-    info->sweep_ms = elapsed(c->ev[1], c->ev[2]);
-    info->total_ms = elapsed(c->ev[0], c->ev[3]);
+    info->sweep_ms = ev ? elapsed(ev[1], ev[2]) : std::numeric_limits<double>::quiet_NaN();
+    info->total_ms = ev ? elapsed(ev[0], ev[3]) : std::numeric_limits<double>::quiet_NaN();
     info->final_rel_resid = std::numeric_limits<double>::quiet_NaN();
   }
   if (hi[4 + CTL_NONFINITE]) return fail(HPSCD_ENONFINITE, "a system holds a non-finite value");
@@ -723,10 +761,29 @@ hpscd_status solve_batched(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, co
   return HPSCD_OK;
 }
 
-int batched_block(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, const hpscd_opts* o) {
-  if (o->block > 0) return o->block;
+int batched_grid(hpscd_ctx* c, const BatchPlan& bp, int B) {
+  const int per_cu = batched_max_blocks_per_cu(B);
+  return std::max(1, std::min((int)bp.items.size(), std::max(1, per_cu) * c->cus));
+}
+
+hpscd_status solve_batched(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, const float* Xpool, const float* ypool,
+                           const float* a0pool, const hpscd_opts* o, int B, int64_t wave_max_m, float* apool,
+                           double* hist, int32_t* sweeps_done, int32_t* converged, double* final_rel,
+                           hpscd_info* info, hipStream_t st) {
+  BatchPlan bp;
+  BatchLayout L;
+  hpscd_status rc = prepare_batch(c, c->bw, count, sys, a0pool != nullptr, o, B, wave_max_m, bp, L, st);
+  if (rc != HPSCD_OK) return rc;
+  if ((rc = enqueue_batch(c, c->bw, bp, L, Xpool, ypool, a0pool, o, B, apool, c->ev, st)) != HPSCD_OK) return rc;
+  return collect_batch(c, c->bw, L, sys, !(o->flags & HPSCD_F_NO_FINAL_CHECK), B, batched_grid(c, bp, B), hist,
+                       sweeps_done, converged, final_rel, info, c->ev, st);
+}
+
+Tuned batched_choice(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, const hpscd_opts* o) {
   auto it = c->tuned.find(batch_key(count, sys));
-  return it != c->tuned.end() ? it->second.B : 1;
+  Tuned t = it != c->tuned.end() ? it->second : Tuned{1, batched_rows_per_wave()};
+  if (o->block > 0) t.B = o->block;
+  return t;
 }
 
 }  // namespace
@@ -741,10 +798,10 @@ hpscd_status hpscd_solve_batched_f32(hpscd_ctx* ctx, int32_t count, const hpscd_
     hpscd_status rc = validate_batch(count, sys, Xpool, ypool, opts, apool);
     if (rc != HPSCD_OK) return rc;
     if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
-    const int B = batched_block(ctx, count, sys, opts);
-    if (!batched_variant_exists(B)) return fail(HPSCD_EINVAL, "batched block %d is not built", B);
-    return solve_batched(ctx, count, sys, Xpool, ypool, a0pool, opts, B, apool, hist, sweeps_done, converged,
-                         final_rel_resid, info, (hipStream_t)stream);
+    const Tuned t = batched_choice(ctx, count, sys, opts);
+    if (!batched_variant_exists(t.B)) return fail(HPSCD_EINVAL, "batched block %d is not built", t.B);
+    return solve_batched(ctx, count, sys, Xpool, ypool, a0pool, opts, t.B, t.wave_max_m, apool, hist, sweeps_done,
+                         converged, final_rel_resid, info, (hipStream_t)stream);
   } catch (...) {
     return fail(HPSCD_ENOMEM, "host allocation failure");
   }
@@ -756,23 +813,123 @@ hpscd_status hpscd_autotune_batched(hpscd_ctx* ctx, int32_t count, const hpscd_s
     hpscd_status rc = validate_batch(count, sys, Xpool, ypool, opts, apool);
     if (rc != HPSCD_OK) return rc;
     if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
+    // Candidates: the block size B (columns per reduction round) and the
+    // work split (systems small enough for one wave share a workgroup four
+    // ways, or every system gets a whole workgroup).
     double best = 1e300;
-    int bestB = 1;
+    Tuned choice{1, batched_rows_per_wave()};
     for (int B : {1, 2, 4}) {
       if (!batched_variant_exists(B)) continue;
-      double t = 1e300;
-      for (int rep = 0; rep < 2; ++rep) {
-        hpscd_info inf;
-        rc = solve_batched(ctx, count, sys, Xpool, ypool, nullptr, opts, B, apool, nullptr, nullptr, nullptr,
-                           nullptr, &inf, (hipStream_t)stream);
-        if (rc != HPSCD_OK) return rc;
-        t = std::min(t, inf.total_ms);
+      for (int64_t split : {(int64_t)batched_rows_per_wave(), (int64_t)0}) {
+        double t = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+          hpscd_info inf;
+          rc = solve_batched(ctx, count, sys, Xpool, ypool, nullptr, opts, B, split, apool, nullptr, nullptr,
+                             nullptr, nullptr, &inf, (hipStream_t)stream);
+          if (rc != HPSCD_OK) return rc;
+          t = std::min(t, inf.total_ms);
+        }
+        if (t < best) { best = t; choice = Tuned{B, split}; }
       }
-      if (t < best) { best = t; bestB = B; }
     }
-    ctx->tuned[batch_key(count, sys)] = Tuned{bestB};
+    ctx->tuned[batch_key(count, sys)] = choice;
     g_err.clear();
     return HPSCD_OK;
+  } catch (...) {
+    return fail(HPSCD_ENOMEM, "host allocation failure");
+  }
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------- batched graph plan
+struct hpscd_batch_plan {
+  hpscd_ctx* ctx = nullptr;
+  BatchWork w;
+  BatchPlan bp;
+  BatchLayout L;
+  std::vector<hpscd_sys> sys;
+  bool check = true;
+  int B = 1, grid = 1;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+void hpscd_batched_plan_destroy(hpscd_batch_plan* p) {
+  if (!p) return;
+  if (p->ctx) (void)hipSetDevice(p->ctx->device);
+  if (p->cap) (void)hipStreamSynchronize(p->cap);
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap) (void)hipStreamDestroy(p->cap);
+  p->w.release();
+  delete p;
+}
+
+hpscd_status hpscd_batched_plan_create(hpscd_ctx* ctx, int32_t count, const hpscd_sys* sys, const float* Xpool,
+                                       const float* ypool, const float* a0pool, const hpscd_opts* opts,
+                                       float* apool, hpscd_batch_plan** out) {
+  if (!out) return fail(HPSCD_EINVAL, "out is NULL");
+  *out = nullptr;
+  hpscd_batch_plan* p = nullptr;
+  try {
+    hpscd_status rc = validate_batch(count, sys, Xpool, ypool, opts, apool);
+    if (rc != HPSCD_OK) return rc;
+    if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
+    const Tuned t = batched_choice(ctx, count, sys, opts);
+    if (!batched_variant_exists(t.B)) return fail(HPSCD_EINVAL, "batched block %d is not built", t.B);
+    HIP_TRY(hipSetDevice(ctx->device));
+    p = new hpscd_batch_plan();
+    p->ctx = ctx;
+    p->sys.assign(sys, sys + count);
+    p->check = !(opts->flags & HPSCD_F_NO_FINAL_CHECK);
+    p->B = t.B;
+    if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
+      hpscd_batched_plan_destroy(p);
+      return fail(HPSCD_EDEVICE, "stream creation failed");
+    }
+    rc = prepare_batch(ctx, p->w, count, sys, a0pool != nullptr, opts, t.B, t.wave_max_m, p->bp, p->L, p->cap);
+    if (rc != HPSCD_OK) { hpscd_batched_plan_destroy(p); return rc; }
+    p->grid = batched_grid(ctx, p->bp, t.B);
+    if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      hpscd_batched_plan_destroy(p);
+      return fail(HPSCD_EDEVICE, "graph capture could not start");
+    }
+    rc = enqueue_batch(ctx, p->w, p->bp, p->L, Xpool, ypool, a0pool, opts, t.B, apool, nullptr, p->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->cap, &g);
+    p->graph = g;
+    if (rc != HPSCD_OK) { hpscd_batched_plan_destroy(p); return rc; }
+    if (ec != hipSuccess || !g || hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      hpscd_batched_plan_destroy(p);
+      return fail(HPSCD_EDEVICE, "graph capture or instantiation failed");
+    }
+    *out = p;
+    g_err.clear();
+    return HPSCD_OK;
+  } catch (...) {
+    if (p) hpscd_batched_plan_destroy(p);
+    return fail(HPSCD_ENOMEM, "host allocation failure");
+  }
+}
+
+hpscd_status hpscd_batched_plan_launch(hpscd_batch_plan* p, void* stream) {
+  if (!p || !p->exec) return fail(HPSCD_EINVAL, "plan is NULL");
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  HIP_TRY(hipGraphLaunch(p->exec, (hipStream_t)stream));
+  return HPSCD_OK;
+}
+
+hpscd_status hpscd_batched_plan_results(hpscd_batch_plan* p, double* hist, int32_t* sweeps_done, int32_t* converged,
+                                        double* final_rel_resid, hpscd_info* info, void* stream) {
+  if (!p) return fail(HPSCD_EINVAL, "plan is NULL");
+  try {
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    return collect_batch(p->ctx, p->w, p->L, p->sys.data(), p->check, p->B, p->grid, hist, sweeps_done, converged,
+                         final_rel_resid, info, nullptr, (hipStream_t)stream);
   } catch (...) {
     return fail(HPSCD_ENOMEM, "host allocation failure");
   }

@@ -89,6 +89,12 @@ _SIGS = {
                                                _dp, _IP, _vp]),
     "hpscd_autotune_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Sys), _vp, _vp, _OP, _vp, _vp]),
     "hpscd_abort": (ctypes.c_int, [_vp]),
+    "hpscd_batched_plan_create": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Sys), _vp, _vp, _vp, _OP, _vp,
+                                                 ctypes.POINTER(_vp)]),
+    "hpscd_batched_plan_launch": (ctypes.c_int, [_vp, _vp]),
+    "hpscd_batched_plan_results": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int32),
+                                                  ctypes.POINTER(ctypes.c_int32), _dp, _IP, _vp]),
+    "hpscd_batched_plan_destroy": (None, [_vp]),
     "hpscd_mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.POINTER(_vp)]),
     "hpscd_mlp_destroy": (None, [_vp]),
@@ -324,6 +330,60 @@ def solve_batched(Xpool, ypool, table, a0pool=None, *, max_sweeps=100, stop=STOP
     return BatchResult(a, hist, sw, cv, fr, info.as_dict())
 
 
+class BatchPlan:
+    """A batched solve recorded once as a HIP graph and replayed.  The pools
+    are bound by address (keep the tensors alive; their contents may change
+    between launches).  ``launch()`` queues a replay on the current stream;
+    ``results()`` waits and returns a BatchResult (info times are NaN)."""
+
+    def __init__(self, Xpool, ypool, table, a0pool=None, apool=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0,
+                 block=0, flags=0, tols=None):
+        torch = _torch()
+        _need_cuda(Xpool, "Xpool", torch.float32)
+        _need_cuda(ypool, "ypool", torch.float32)
+        _need_cuda(a0pool, "a0pool", torch.float32)
+        table = np.asarray(table, dtype=np.int64).reshape(-1, 6)
+        self.count = len(table)
+        a_size = int((table[:, 5] + table[:, 1]).max())
+        self.a = apool if apool is not None else torch.zeros(a_size, dtype=torch.float32, device=Xpool.device)
+        _need_cuda(self.a, "apool", torch.float32)
+        self._keep = (Xpool, ypool, a0pool, self.a)
+        self.max_sweeps = int(max_sweeps)
+        opts = make_opts(max_sweeps, stop, tol, 0, 0, block, flags)
+        h = _vp()
+        self._ctx = context(Xpool.device.index)
+        _check(_lib.hpscd_batched_plan_create(self._ctx, self.count, _sys_array(table, tols), _ptr(Xpool),
+                                              _ptr(ypool), _ptr(a0pool), ctypes.byref(opts), _ptr(self.a),
+                                              ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        _check(_lib.hpscd_batched_plan_launch(self._h, _stream()))
+
+    def results(self, want_hist=False) -> BatchResult:
+        hist = np.full((self.count, self.max_sweeps + 1), np.nan) if want_hist else None
+        sw = np.zeros(self.count, np.int32)
+        cv = np.zeros(self.count, np.int32)
+        fr = np.zeros(self.count)
+        info = Info()
+        _check(_lib.hpscd_batched_plan_results(
+            self._h, hist.ctypes.data_as(_dp) if hist is not None else None,
+            sw.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            fr.ctypes.data_as(_dp), ctypes.byref(info), _stream()))
+        return BatchResult(self.a, hist, sw, cv, fr, info.as_dict())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hpscd_batched_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def autotune_batched(Xpool, ypool, table, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, a_size=None):
     torch = _torch()
     table = np.asarray(table, dtype=np.int64).reshape(-1, 6)
@@ -385,10 +445,13 @@ class MLP:
         _check(_lib.hpscd_mlp_get_params(self._h, _ptr(flat), _stream()))
         return flat
 
-    def forward(self, x):
+    def forward(self, x, out=None):
         torch = _torch()
         x = self._vec(x, "x", self.shape[0])
-        y = torch.empty(x.shape[0], self.shape[3], dtype=torch.float32, device=x.device)
+        y = torch.empty(x.shape[0], self.shape[3], dtype=torch.float32, device=x.device) if out is None else out
+        _need_cuda(y, "out", torch.float32)
+        if y.numel() != x.shape[0] * self.shape[3]:
+            raise ValueError("out must hold batch * n_out values")
         _check(_lib.hpscd_mlp_forward(self._h, x.shape[0], _ptr(x), _ptr(y), _stream()))
         return y
 

@@ -120,9 +120,10 @@ class WarmStart:
         p[-n_out:] = p[-n_out:] * sd + mu
         self.set_params(p)
 
-    def predict(self, feats):
-        """Initial guesses (count, n_out) for the systems with these features."""
-        return self.net.forward(feats.contiguous())
+    def predict(self, feats, out=None):
+        """Initial guesses (count, n_out) for the systems with these features
+        (written into ``out`` when given, e.g. the a0 pool of a BatchPlan)."""
+        return self.net.forward(feats.contiguous(), out=out)
 
     def save(self, path: str):
         np.savez(path, shape=np.asarray(self.shape, dtype=np.int64), params=self.params().cpu().numpy())

@@ -142,3 +142,17 @@ def test_mlp_create_rejects_bad_widths(hp):
     assert hp._lib.hpscd_mlp_num_params(None) == 0
     assert hp._lib.hpscd_mlp_forward(None, 1, 16, 16, None) == hp.EINVAL
     hp._lib.hpscd_mlp_destroy(None)
+
+
+def test_batched_plan_rejects_bad_arguments(hp):
+    o = hp.make_opts(5)
+    h = ctypes.c_void_p()
+    table = hp._sys_array([[100, 10, 0, 100, 0, 0]])
+    assert hp._lib.hpscd_batched_plan_create(None, 1, table, 4096, 64, None, ctypes.byref(o), 128,
+                                             ctypes.byref(h)) == hp.EINVAL
+    assert "ctx" in hp.last_error()
+    assert hp._lib.hpscd_batched_plan_create(None, 0, table, 4096, 64, None, ctypes.byref(o), 128,
+                                             ctypes.byref(h)) == hp.EINVAL
+    assert hp._lib.hpscd_batched_plan_launch(None, None) == hp.EINVAL
+    assert hp._lib.hpscd_batched_plan_results(None, None, None, None, None, None, None) == hp.EINVAL
+    hp._lib.hpscd_batched_plan_destroy(None)

@@ -165,3 +165,33 @@ def test_bf16_time_to_tolerance_is_confirmed(lib, size):
     assert abs(r.info["refreshes"] - ref.refreshes) <= 1
     if r.info["cols_done"] == ref.cols:
         assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
+
+
+def test_batched_graph_replays_match_eager(lib):
+    """The recorded batched solve, replayed several times with eager work and
+    host waits in between, gives the eager call's results every time; a new
+    a0 written into the bound pool is picked up by the next replay."""
+    import torch
+    b = gen.batch(seed=14, count=48, m_lo=200, m_hi=8192, n_lo=4, n_hi=100)
+    Xp, yp = dev(b.Xpool), dev(b.ypool)
+    say("graph plan")
+    eager = lib.solve_batched(Xp, yp, b.table, max_sweeps=15, stop=lib.STOP_REL_CHANGE, tol=1e-6, want_hist=True)
+    a0 = torch.zeros(eager.a.numel(), dtype=torch.float32, device="cuda")
+    plan = lib.BatchPlan(Xp, yp, b.table, a0pool=a0, max_sweeps=15, stop=lib.STOP_REL_CHANGE, tol=1e-6)
+    for rep in range(3):
+        plan.launch()
+        got = plan.results(want_hist=True)
+        assert torch.equal(got.a, eager.a), rep
+        assert np.array_equal(got.sweeps, eager.sweeps)
+        assert np.array_equal(got.hist, eager.hist, equal_nan=True)
+        np.testing.assert_allclose(got.final_rel_resid, eager.final_rel_resid, rtol=1e-12)
+        # unrelated eager work between replays
+        lib.solve_batched(Xp, yp, b.table, max_sweeps=2)
+        torch.cuda.synchronize()
+    a0.copy_(eager.a)  # warm start from the converged answer through the bound pool
+    warm = lib.solve_batched(Xp, yp, b.table, a0pool=a0.clone(), max_sweeps=15, stop=lib.STOP_REL_CHANGE, tol=1e-6)
+    plan.launch()
+    got = plan.results()
+    assert torch.equal(got.a, warm.a)
+    assert np.array_equal(got.sweeps, warm.sweeps)
+    plan.close()
