@@ -280,7 +280,7 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
                             nullptr, st));
     e0 = c->e0.as<float>();
   }
-  const bool pipelined = pl.D == 4;
+  const bool pipelined = pl.grid && pl.D == 4;  // (one workgroup: D = 4 is a 4-block ring)
   HIP_TRY(launch_colgram(Xs, bf16, ldxs, m, n, B, c->rdn.as<double>(), c->gram.as<double>(),
                          pipelined ? c->cross.as<double>() : nullptr, partial, partial_cap,
                          ctl, &ctl64[C64_ZERO_COLS], st));

@@ -195,3 +195,31 @@ def test_batched_graph_replays_match_eager(lib):
     assert torch.equal(got.a, warm.a)
     assert np.array_equal(got.sweeps, warm.sweeps)
     plan.close()
+
+
+def test_batched_full_size_sampled(lib):
+    """The 4096-system batch in the configuration the benchmark times
+    (autotuned, recorded as a graph, relative-change stop 1e-6): sampled
+    systems (the largest, the smallest, and random ones) against the oracle
+    run for the sweep count the GPU reports, and against the oracle's own stop."""
+    b = gen.batch()
+    Xp, yp = dev(b.Xpool), dev(b.ypool)
+    kw = dict(max_sweeps=100, stop=lib.STOP_REL_CHANGE, tol=1e-6)
+    say("batched full size: autotune")
+    lib.autotune_batched(Xp, yp, b.table, **kw)
+    plan = lib.BatchPlan(Xp, yp, b.table, **kw)
+    plan.launch()
+    r = plan.results()
+    a = r.a.cpu().numpy()
+    assert np.all(r.converged == 1)
+    work = b.table[:, 0] * b.table[:, 1]
+    order = np.argsort(work)
+    rng = np.random.default_rng(0)
+    sample = np.unique(np.concatenate([order[:6], order[-6:], rng.choice(b.count, 12, replace=False)]))
+    for i in sample:
+        s = b.system(int(i))
+        ao = b.table[i, 5]
+        ref = oracle.solve(s.Xt, s.y, s.m, max_sweeps=int(r.sweeps[i]))
+        assert rel(a[ao: ao + s.n], ref.a) <= 1e-5, (i, s.m, s.n)
+        own = oracle.solve(s.Xt, s.y, s.m, max_sweeps=100, stop=oracle.STOP_REL_CHANGE, tol=1e-6)
+        assert abs(own.sweeps - int(r.sweeps[i])) <= 1, (i, own.sweeps, r.sweeps[i])

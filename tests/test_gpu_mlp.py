@@ -138,3 +138,47 @@ def test_learned_warm_start_gains(lib):
     # the warm start is a starting point only: its answers are judged by the same FP64 check
     assert np.all(np.isfinite(warm.final_rel_resid))
     assert np.median(warm.final_rel_resid / np.maximum(ref.tau, 1e-30)) <= 1.01
+
+
+def test_warm_start_full_size_sampled(lib):
+    """The held-out set at full size (2000 systems, m = 4096, n = 64) in the
+    configuration the benchmark times (network forward into the a0 pool of a
+    recorded batched solve with per-system tolerances): sampled rows of a0
+    against the oracle's forward with the trained parameters, and sampled
+    solves against the oracle run from the same a0 for the same sweeps."""
+    from paper_2104_12570_amd import warmstart
+    from workloads.rbf_torch import rbf_pool
+    import torch
+    K = 100
+    Ptr, Ttr = gen.rbf_params(5, 2048)
+    Pte, Tte = gen.rbf_params(6, 2000)
+    say("warm start full size: labels")
+    Xtr, ytr, tabtr = rbf_pool(Ptr, Ttr, device="cuda")
+    lab = warmstart.label(Xtr, ytr, tabtr, K)
+    ws = warmstart.WarmStart(13, 64, seed=0)
+    ws.fit(dev(gen.rbf_features(Ptr)), lab.a, epochs=10, batch=512, lr=2e-3)
+    del Xtr, ytr
+    Xte, yte, tabte = rbf_pool(Pte, Tte, device="cuda")
+    ref = warmstart.label(Xte, yte, tabte, K)
+    feats = gen.rbf_features(Pte)
+    a0 = torch.empty(2000 * 64, dtype=torch.float32, device="cuda")
+    plan = lib.BatchPlan(Xte, yte, tabte, a0pool=a0, max_sweeps=K, stop=lib.STOP_REL_RESID, tols=ref.tau)
+    say("warm start full size: solve")
+    ws.predict(dev(feats), out=a0)
+    plan.launch()
+    r = plan.results()
+    params = ws.params().cpu().numpy().astype(np.float64)
+    a0h = a0.view(2000, 64).cpu().numpy()
+    a = r.a.cpu().numpy()
+    Xh, yh = Xte.cpu().numpy(), yte.cpu().numpy()
+    rng = np.random.default_rng(1)
+    for i in rng.choice(2000, 10, replace=False):
+        fwd = mo.forward(params, FULL, feats[i: i + 1].astype(np.float64))[0]
+        assert rel(a0h[i], fwd) <= 1e-5, i
+        Xt = Xh[i * 64 * 4096: (i + 1) * 64 * 4096].reshape(64, 4096)
+        y = yh[i * 4096: (i + 1) * 4096]
+        o = oracle.solve(Xt, y, 4096, a0=a0h[i].astype(np.float64), max_sweeps=int(r.sweeps[i]))
+        say(i, r.sweeps[i], rel(a[i * 64: (i + 1) * 64], o.a), r.final_rel_resid[i],
+            oracle.final_rel_resid(Xt, y, 4096, o.a))
+        assert rel(a[i * 64: (i + 1) * 64], o.a) <= 1e-5, i
+        assert r.final_rel_resid[i] == pytest.approx(oracle.final_rel_resid(Xt, y, 4096, o.a), rel=1e-4)
