@@ -223,3 +223,21 @@ def test_batched_full_size_sampled(lib):
         assert rel(a[ao: ao + s.n], ref.a) <= 1e-5, (i, s.m, s.n)
         own = oracle.solve(s.Xt, s.y, s.m, max_sweeps=100, stop=oracle.STOP_REL_CHANGE, tol=1e-6)
         assert abs(own.sweeps - int(r.sweeps[i])) <= 1, (i, own.sweeps, r.sweeps[i])
+
+
+def test_batched_size_boundaries(lib):
+    """Systems at the edges of the batched kernel's work split: m = 2048 (the
+    largest that one wave holds), 2049 (the smallest given a whole
+    workgroup), 8192 (the largest accepted), tiny m, n = 1 and n close to m."""
+    rng = np.random.default_rng(77)
+    sizes = [(2048, 40), (2049, 40), (8192, 100), (8192, 1), (2, 1), (3, 2), (100, 90), (64, 50), (1000, 7)]
+    systems = [gen.make_system(rng, m, n, noise=0.01, pad=np.nan) for m, n in sizes]
+    b = gen.pack(systems)
+    say("batched boundaries")
+    r = lib.solve_batched(dev(b.Xpool), dev(b.ypool), b.table, max_sweeps=20, want_hist=True)
+    a = r.a.cpu().numpy()
+    for i, s in enumerate(systems):
+        ref = oracle.solve(s.Xt, s.y, s.m, max_sweeps=20)
+        ao = b.table[i, 5]
+        assert rel(a[ao: ao + s.n], ref.a) <= 1e-5, sizes[i]
+        assert np.all(np.abs(r.hist[i] - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0]), sizes[i]

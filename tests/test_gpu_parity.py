@@ -86,7 +86,8 @@ def test_tall_small_200_sweeps(lib, team, block):
     assert r.info["final_rel_resid"] == pytest.approx(oracle.final_rel_resid(s.Xt, s.y, s.m, ref.a), rel=1e-4)
 
 
-@pytest.mark.parametrize("m,n", [(1, 3), (5, 2), (1999, 37), (2001, 9), (4093, 21), (4096, 64)])
+@pytest.mark.parametrize("m,n", [(1, 3), (5, 2), (7, 50), (1999, 37), (2001, 9), (4093, 21), (4096, 64),
+                                 (4097, 13), (8193, 5)])
 def test_ragged_shapes(lib, m, n):
     """Rows not a multiple of the 16-byte chunk, columns not a multiple of the
     block, NaN padding rows."""
