@@ -367,7 +367,11 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic("k_sweep_f32_tall_1000000x256", sweeps)
             if (s.m, s.n, args.fixed_sweeps) == (1_000_000, 256, 0) else None,
-            "kernel": "k_sweep (persistent grid)", "alg_bytes_per_launch": alg_bytes,
+            "kernel": {5: "k_sweep_px (persistent grid, polling waves fed through LDS)",
+                       2: "k_sweep (persistent grid, 2-block ring)",
+                       3: "k_sweep (persistent grid, 3-block ring)"}.get(info["kernel_kind"],
+                                                                         f"sweep kernel kind {info['kernel_kind']}"),
+            "alg_bytes_per_launch": alg_bytes,
             "launch_ms": sweep_ms,
         },
     }

@@ -73,7 +73,9 @@ typedef struct {
   int32_t team_threads; /* threads per workgroup; 0 = library choice */
   int32_t depth;        /* kernel kind; 0 = library choice.  2, 3: prefetch ring of 2 or 3 blocks;
                            4: pipelined grid kernel, or a 4-block ring for one workgroup;
-                           12, 13: grid kernel with a dedicated reduction wave, ring of 2 or 3 */
+                           5: grid kernel whose polling waves never wait behind column loads
+                           (their rows arrive through LDS); 12, 13: grid kernel with a
+                           dedicated reduction wave, ring of 2 or 3 */
 } hpscd_opts;
 
 typedef struct {
@@ -90,6 +92,7 @@ typedef struct {
   int32_t refreshes;       /* residual refreshes queued (bf16 form) */
   double sweep_ms;         /* device time of the sweep kernels (HIP events) */
   double total_ms;         /* device time of the whole call (HIP events) */
+  int32_t kernel_kind;     /* sweep kernel used (the values of hpscd_opts.depth); 0 for batched calls */
 } hpscd_info;
 
 /* Fill *o with defaults: max_sweeps 100, HPSCD_STOP_NONE, tol 0, no checks,

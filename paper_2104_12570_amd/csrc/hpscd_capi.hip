@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -132,8 +133,9 @@ hpscd_status validate_opts(const hpscd_opts* o) {
   if (o->refresh_cols < 0) return fail(HPSCD_EINVAL, "refresh_cols must be >= 0");
   if (o->block != 0 && o->block != 1 && o->block != 2 && o->block != 4 && o->block != 8)
     return fail(HPSCD_EINVAL, "block must be 0, 1, 2, 4 or 8 (got %d)", o->block);
-  if (o->depth != 0 && o->depth != 2 && o->depth != 3 && o->depth != 4 && o->depth != 12 && o->depth != 13)
-    return fail(HPSCD_EINVAL, "depth (kernel kind) must be 0, 2, 3, 4, 12 or 13 (got %d)", o->depth);
+  if (o->depth != 0 && o->depth != 2 && o->depth != 3 && o->depth != 4 && o->depth != 5 && o->depth != 12 &&
+      o->depth != 13)
+    return fail(HPSCD_EINVAL, "depth (kernel kind) must be 0, 2, 3, 4, 5, 12 or 13 (got %d)", o->depth);
   if ((o->flags & HPSCD_F_FORCE_GRID) && (o->flags & HPSCD_F_FORCE_WG))
     return fail(HPSCD_EINVAL, "FORCE_GRID and FORCE_WG are exclusive");
   if ((int64_t)o->max_sweeps + 1 > (int64_t)1 << 30) return fail(HPSCD_EINVAL, "max_sweeps too large");
@@ -164,9 +166,11 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
   else grid = m > 256 * (bf16 ? 2 : 4) * VEC;
   std::vector<std::pair<int, int>> shapes;  // (T, R) candidates, smallest first
   if (grid) {
+    // FP32: the polling-wave kernel (kind 5) with 256 threads x 4 chunks first
+    // (up to 256 workgroups, 1,048,576 rows), then the plain grid kernel
     if (bf16) shapes = {{1024, 1}, {512, 1}};
-    else if (m >= 256 * 1024 * 4) shapes = {{512, 2}, {1024, 1}, {256, 4}};
-    else shapes = {{256, 1}, {256, 2}, {512, 2}, {1024, 1}};
+    else if (m >= 256 * 1024 * 4) shapes = {{256, 4}, {512, 2}, {1024, 1}};
+    else shapes = {{256, 4}, {256, 1}, {256, 2}, {512, 2}, {1024, 1}};
   } else {
     if (bf16) shapes = {{256, 1}, {256, 2}};
     else shapes = {{256, 2}, {256, 4}};
@@ -188,7 +192,7 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
   if (grid && o->depth == 4 && o->check_cols > 0 && o->stop == HPSCD_STOP_REL_RESID)
     return fail(HPSCD_EINVAL, "the pipelined kernel (depth 4) tests the stop rule only at sweep ends");
   if (o->depth != 0) kinds = {o->depth};
-  else if (grid) kinds = {2, 3};  // measured fastest on the 1M x 256 system; 4, 12, 13 are selectable
+  else if (grid) kinds = {5, 2, 3};  // measured fastest on the 1M x 256 system; 4, 12, 13 are selectable
   else kinds = {4, 3, 2};         // one workgroup: the deepest ring hides the most load latency
   auto kind_of = [&](int T, int R, int b) {
     for (int k : kinds)
@@ -214,6 +218,19 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
   }
   return fail(HPSCD_EINVAL, "no kernel variant fits m=%lld (%s team, block %d)", (long long)m,
               grid ? "grid" : "workgroup", B);
+}
+
+// Wait between publishing a grid reduction's words and the first poll of
+// the others' words.  A poll that arrives before the slowest workgroup's
+// words are visible costs a second round trip (and, in the plain grid kernel,
+// waits behind the next block's column loads); the wait that minimised the
+// block time grows with the number of workgroups (measured on the 1M x 256
+// system and on 64k..500k-row systems).
+uint32_t poll_delay_ticks(const Plan& pl) {
+  if (!pl.grid) return 0;
+  if (pl.D == 5) return (uint32_t)std::min(240.0, 80.0 + 0.6 * pl.P);
+  if (pl.D == 2 || pl.D == 3) return (uint32_t)std::min(160.0, 0.65 * pl.P);
+  return 0;
 }
 
 hpscd_status validate_single(int64_t m, int64_t n, const void* X, int64_t ldx, int vec, const void* y,
@@ -308,6 +325,7 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   A.check_cols = (o->stop == HPSCD_STOP_REL_RESID) ? o->check_cols : 0;
   A.P = pl.P;
   A.timeout_ticks = kTimeoutTicks;
+  A.poll_delay = poll_delay_ticks(pl);
   const int64_t total = (int64_t)o->max_sweeps * nb + 1;
   const int64_t seg = (o->refresh_cols > 0) ? std::max<int64_t>(1, o->refresh_cols / B) : total;
   const bool coop = pl.grid && !(o->flags & HPSCD_F_NO_COOP);
@@ -386,6 +404,7 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
     info->refreshes = refreshes;
     info->sweep_ms = elapsed(c->ev[1], c->ev[2]);
     info->total_ms = elapsed(c->ev[0], c->ev[3]);
+    info->kernel_kind = pl.D;
   }
   if (hc->ctl[CTL_NONFINITE]) return fail(HPSCD_ENONFINITE, "X or y holds a non-finite value");
   if (hc->ctl[CTL_ERR] == ERR_TIMEOUT) return fail(HPSCD_ETIMEOUT, "grid reduction timed out");

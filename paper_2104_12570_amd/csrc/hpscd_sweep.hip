@@ -41,22 +41,32 @@ template <int B>
 struct Coef {
   static constexpr int NG = B * (B - 1) / 2;
   static constexpr int NGD = NG + B;
-  static constexpr int NCR = (NGD + WAVE - 1) / WAVE;
-  double v[NCR];
+  static constexpr int NCR = (B + WAVE - 1) / WAVE;                     // registers of reciprocal norms
+  static constexpr int NCG = NG > 0 ? (NG + WAVE - 1) / WAVE : 0;       // registers of Gram entries
+  double vr[NCR];
+  double vg[NCG > 0 ? NCG : 1];
 
+  // Every lane issues the same loads (indices clamped into range; lanes past
+  // the last entry hold a copy that is never read), and nothing selects on
+  // the loaded values, so the compiler can leave the loads in flight and
+  // count them exactly when it waits.
   __device__ inline void load(const double* rdn, const double* gram, int64_t bi, int lane) {
     // bi: block index within the sweep
 #pragma unroll
     for (int r = 0; r < NCR; ++r) {
       const int q = r * WAVE + lane;
-      double x = 0.0;
-      if (q < B) x = rdn[bi * B + q];
-      else if (q < NGD) x = gram[bi * NG + (q - B)];
-      v[r] = x;
+      vr[r] = rdn[bi * B + (q < B ? q : B - 1)];
+    }
+#pragma unroll
+    for (int r = 0; r < NCG; ++r) {
+      const int q = r * WAVE + lane;
+      vg[r] = gram[bi * NG + (q < NG ? q : NG - 1)];
     }
   }
-  __device__ inline double get(int q) const {  // q is a compile-time constant after unrolling
-    return readlane_f64(v[q / WAVE], q % WAVE);
+  // Entry q of the block's table (q < B: reciprocal norm, then the Gram
+  // entries); q is a compile-time constant after unrolling.
+  __device__ inline double get(int q) const {
+    return q < B ? readlane_f64(vr[q / WAVE], q % WAVE) : readlane_f64(vg[(q - B) / WAVE], (q - B) % WAVE);
   }
 };
 
@@ -83,6 +93,8 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
   constexpr int NV = B + 1;
   constexpr int MAXC = 8;                       // up to 512 workgroups in a grid team
   constexpr int MAXT = (NV * MAXC + NW - 1) / NW < 8 ? (NV * MAXC + NW - 1) / NW : 8;  // poll tasks per wave
+  constexpr int CPW = (MAXC + NW - 1) / NW;  // chunks of 64 workgroups polled by one wave
+  constexpr int NWD = NV * CPW;              // poll words per lane
   __shared__ float red[2][NW][NV];
   __shared__ double gsum[2][NV][MAXC];
   __shared__ int sflag;
@@ -120,23 +132,25 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
   // Columns of one block are read through a buffer resource based at the
   // block's first column: one 32-bit lane offset per chunk, one scalar offset
   // per column, and loads past the last column of the system return zero.
-  auto load_block = [&](raw (&x)[B][R], Coef<B>& cf, int bi) {
+  auto load_cols = [&](raw (&x)[B][R], int bi) {
     const int j0 = bi * B;
     const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
     const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
     const uint32_t nrec = span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         const_cast<char*>(reinterpret_cast<const char*>(A.X) + (int64_t)j0 * col_bytes), 0, (int)nrec, 0x00020000);
+    // Unconditional loads: rows past m read padding, the next column or (past
+    // the resource's range) zero, and are masked before use; a fixed number
+    // of loads per block keeps the compiler's wait counts exact.
 #pragma unroll
     for (int l = 0; l < B; ++l) {
 #pragma unroll
-      for (int c = 0; c < R; ++c) {
-        if (lim[c] > 0)
-          x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
-        else
-          x[l][c] = S::zero();
-      }
+      for (int c = 0; c < R; ++c)
+        x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
     }
+  };
+  auto load_block = [&](raw (&x)[B][R], Coef<B>& cf, int bi) {
+    load_cols(x, bi);
     cf.load(A.rdn, A.gram, bi, lane);
   };
 
@@ -166,9 +180,11 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
     auto prefetch = [&]() {
       if constexpr (sizeof(pf) == sizeof(cur)) load_block(pf, cpf, pbi);
     };
-    if constexpr (!GRID) {
-      if (has_next) prefetch();
-    }
+    // The block D-1 ahead is requested even past the end of the launch (it is
+    // a valid block of the sweep, never used), so every step issues the same
+    // loads.
+    (void)has_next;
+    if constexpr (!GRID) prefetch();
 
     float p[NV];
 #pragma unroll
@@ -213,67 +229,83 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
       // loads at once, then the next block's loads, then re-polls only words
       // whose sequence number is not yet current.
       uint64_t* slot_base = A.slots + (int64_t)par * NV * A.P;
+      // With two blocks resident, the next block's coefficients are requested
+      // first and its columns right behind this wave's first poll loads: the
+      // wait for the poll words then leaves the columns in flight.  (Vector
+      // loads return in issue order, so a re-poll does wait behind them.)
+      if constexpr (D == 2) {
+        if constexpr (sizeof(pf) == sizeof(cur)) cpf.load(A.rdn, A.gram, pbi, lane);
+      }
       if (tid < NV) {
         float sacc = 0.f;
 #pragma unroll
         for (int w = 0; w < NW; ++w) sacc += red[par][w][tid];
         publish(slot_base + (int64_t)tid * A.P + wg, seq, sacc);
       }
+      if (A.poll_delay) {
+        const uint64_t t0d = now_ticks();
+        while (now_ticks() - t0d < A.poll_delay) __builtin_amdgcn_s_sleep(2);
+      }
       const int ncn = (A.P + WAVE - 1) / WAVE;
-      const int ntask = NV * ncn;
       bool timed_out = false;
-      for (int t0 = wave; t0 < ntask; t0 += NW * MAXT) {
-        uint64_t w[MAXT];
+      // Wave w reads chunk c = w (+ NW, ...) of 64 workgroups for every value:
+      // word (l, c*64 + lane).  Every lane issues the same loads (lanes past
+      // the last workgroup read a valid word and ignore it), no index needs a
+      // division, and nothing selects on a loaded value before the wait, so
+      // the wait for the poll words is an exact count that leaves the column
+      // loads behind them in flight.
+      uint64_t w[NWD];
 #pragma unroll
-        for (int q = 0; q < MAXT; ++q) {
-          const int t = t0 + q * NW;
-          const int l = t / ncn, c = t - l * ncn, idx = c * WAVE + lane;
-          const bool live = t < ntask && idx < A.P;
-          w[q] = live ? peek(slot_base + (int64_t)l * A.P + idx) : ((uint64_t)seq << 32);
+      for (int k = 0; k < CPW; ++k) {
+        const int idx = (wave + k * NW) * WAVE + lane;
+        const bool live = wave + k * NW < MAXC && idx < A.P;
+#pragma unroll
+        for (int l = 0; l < NV; ++l) w[k * NV + l] = peek(slot_base + (int64_t)l * A.P + (live ? idx : 0));
+      }
+      if constexpr (D == 2) {
+        if constexpr (sizeof(pf) == sizeof(cur)) load_cols(pf, pbi);
+      }
+#pragma unroll
+      for (int k = 0; k < CPW; ++k) {
+        const int idx = (wave + k * NW) * WAVE + lane;
+        const bool live = wave + k * NW < MAXC && idx < A.P;
+#pragma unroll
+        for (int l = 0; l < NV; ++l)
+          if (!live) w[k * NV + l] = (uint64_t)seq << 32;
+      }
+      uint64_t tstart = 0;
+      for (int spin = 0;; ++spin) {
+        bool ready = true;
+#pragma unroll
+        for (int q = 0; q < NWD; ++q) ready = ready && ((uint32_t)(w[q] >> 32) == seq);
+        if (ready) break;
+        if (spin == 0) tstart = now_ticks();
+        else if (now_ticks() - tstart > A.timeout_ticks) {
+          timed_out = true;
+          break;
         }
-        // With two blocks resident the next block's loads go out right after
-        // the first poll loads; with three, the block two ahead is requested
-        // only after this wave's poll has completed, so no poll load waits
-        // behind column data (vector loads return in order).
-        if constexpr (D == 2) {
-          if (t0 == wave && has_next) prefetch();
+        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) {
+          const int idx = (wave + k * NW) * WAVE + lane;
+#pragma unroll
+          for (int l = 0; l < NV; ++l)
+            if ((uint32_t)(w[k * NV + l] >> 32) != seq) w[k * NV + l] = peek(slot_base + (int64_t)l * A.P + idx);
         }
-        uint64_t tstart = 0;
-        for (int spin = 0;; ++spin) {
-          bool ready = true;
+      }
 #pragma unroll
-          for (int q = 0; q < MAXT; ++q) ready = ready && ((uint32_t)(w[q] >> 32) == seq);
-          if (ready) break;
-          if (spin == 0) tstart = now_ticks();
-          else if (now_ticks() - tstart > A.timeout_ticks) {
-            timed_out = true;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
+      for (int k = 0; k < CPW; ++k) {
+        const int c = wave + k * NW;
+        if (c < ncn) {  // wave-uniform
+          const int idx = c * WAVE + lane;
 #pragma unroll
-          for (int q = 0; q < MAXT; ++q) {
-            if ((uint32_t)(w[q] >> 32) != seq) {
-              const int t = t0 + q * NW;
-              const int l = t / ncn, c = t - l * ncn, idx = c * WAVE + lane;
-              w[q] = peek(slot_base + (int64_t)l * A.P + idx);
-            }
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < MAXT; ++q) {
-          const int t = t0 + q * NW;
-          if (t < ntask) {  // wave-uniform
-            const int l = t / ncn, c = t - l * ncn, idx = c * WAVE + lane;
-            const double v = wave_sum(idx < A.P ? (double)__uint_as_float((uint32_t)w[q]) : 0.0);
+          for (int l = 0; l < NV; ++l) {
+            const double v = wave_sum(idx < A.P ? (double)__uint_as_float((uint32_t)w[k * NV + l]) : 0.0);
             if (lane == 0) gsum[par][l][c] = v;
           }
         }
       }
-      if constexpr (D == 2) {
-        if (ntask <= wave && has_next) prefetch();
-      } else {
-        if (has_next) prefetch();
-      }
+      if constexpr (D != 2) prefetch();
       if (timed_out) sflag = 1;
       __syncthreads();
       if (sflag) {
@@ -382,6 +414,324 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
       ++k;
     }
   }
+#pragma unroll
+  for (int c = 0; c < R; ++c)
+#pragma unroll
+    for (int i = 0; i < VEC; ++i)
+      if (i < lim[c]) A.e_out[rof[c] + i] = e[c][i];
+}
+
+// --------------------------------------------------------------------------
+// Grid kernel with a polling wave that never waits behind column data.
+//
+// Vector loads of a wave return in issue order, so a wave that has requested
+// the next block's columns sees the result of a later poll of the exchange
+// words only after those columns have arrived: streaming and reduction
+// latency add up.  Here the last wave of each workgroup does all the polling
+// and issues no column loads of its own; its rows of every block are brought
+// into LDS by the other waves with direct-to-LDS buffer loads, issued with
+// their own column loads for the next block right after the partial sums are
+// published.  The next block's columns then stream in while the exchange is
+// in flight.  Arithmetic, reduction order and stop logic are those of k_sweep.
+template <class S, int T, int R, int B, int NPW>
+__global__ void __launch_bounds__(T) k_sweep_px(SolveArgs A) {
+  using raw = typename S::raw_t;
+  constexpr int VEC = S::VEC;
+  constexpr int NW = T / WAVE;
+  constexpr int NV = B + 1;
+  constexpr int NH = NW - NPW;         // waves that stream columns
+  constexpr int MAXC = 4;              // up to 256 workgroups
+  constexpr int CPP = MAXC / NPW;      // chunks of 64 workgroups per polling wave
+  static_assert(NW > NPW && MAXC % NPW == 0, "wave split");
+  __shared__ float red[2][NW][NV];
+  __shared__ raw pbuf[2][NPW][B][R][WAVE];  // the polling waves' rows of two blocks
+  __shared__ double tpart[NPW][NV];
+  __shared__ int sflag;
+
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
+  const bool pollw = wave >= NH;
+  const int pw = pollw ? wave - NH : 0;
+  const int wg = (int)blockIdx.x;
+  const int64_t m = A.m, n = A.n;
+  const int nb = (int)((n + B - 1) / B);
+  if (A.ctl[CTL_NONFINITE] != 0 || A.ctl[CTL_DONE] != 0) return;
+  if (tid == 0) sflag = 0;
+
+  float e[R][VEC];
+  int lim[R];
+  int64_t rof[R];
+  uint32_t boff[R];   // own rows
+  uint32_t boffp[NPW][R];  // the polling waves' rows, lane for lane
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    rof[c] = (int64_t)wg * (T * R * VEC) + (int64_t)VEC * (tid + T * c);
+    const int64_t left = m - rof[c];
+    lim[c] = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
+    boff[c] = (uint32_t)(rof[c] * (16 / VEC));
+#pragma unroll
+    for (int q = 0; q < NPW; ++q) {
+      const int64_t rofp = (int64_t)wg * (T * R * VEC) + (int64_t)VEC * ((NH + q) * WAVE + lane + T * c);
+      boffp[q][c] = (uint32_t)(rofp * (16 / VEC));
+    }
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? A.e0[rof[c] + i] : 0.f;
+  }
+
+  double prev_norm = A.fstat[1];
+  const double ynorm = sqrt(*A.ynorm2);
+  const int64_t nblocks = A.blk_end - A.blk_begin;
+  const int64_t col_bytes = A.ldx * (int64_t)(16 / VEC);
+  raw x0[B][R], x1[B][R];
+  Coef<B> c0, c1;
+
+  auto rsrc = [&](int bi) {
+    const int j0 = bi * B;
+    const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
+    const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
+    const uint32_t nrec = span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span;
+    return __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<char*>(reinterpret_cast<const char*>(A.X) + (int64_t)j0 * col_bytes), 0, (int)nrec, 0x00020000);
+  };
+  // Streaming waves: their own columns into registers and their share of the
+  // polling wave's columns into LDS buffer `pb` (unconditional loads; rows
+  // past m are masked before use).
+  auto load_block = [&](raw (&x)[B][R], int bi, int pb) {
+    const __amdgpu_buffer_rsrc_t rs = rsrc(bi);
+#pragma unroll
+    for (int l = 0; l < B; ++l)
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+        x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
+#pragma unroll
+    for (int q = 0; q < NPW * B * R; ++q) {
+      if (q % NH == wave) {  // wave-uniform
+        const int v = q / (B * R), l = (q / R) % B, c = q % R;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)&pbuf[pb][v][l][c][0],
+                                                  16, (int)boffp[v][c], (int)(l * col_bytes), 0, 0);
+      }
+    }
+  };
+
+  auto finalize = [&](int sdone, bool conv, int64_t cols, double nrm2) {
+    if (wg == 0 && tid == 0) {
+      A.ctl[CTL_SWEEPS] = sdone;
+      A.ctl[CTL_CONVERGED] = conv ? 1 : 0;
+      A.ctl[CTL_DONE] = 1;
+      A.ctl64[C64_COLS] = cols;
+      A.fstat[0] = nrm2;
+    }
+  };
+
+  int bi = (int)(A.blk_begin % nb);
+  int sdone = (int)(A.blk_begin / nb);
+  uint32_t seq = (uint32_t)(A.blk_begin + 1);
+
+  auto step = [&](raw (&cur)[B][R], raw (&pf)[B][R], Coef<B>& ccur, Coef<B>& cpf, int64_t k) -> bool {
+    const int j0 = bi * B;
+    const int nbi = (bi + 1 == nb) ? 0 : bi + 1;
+    const int pb = (int)(k & 1);
+    // this block's columns (registers, and the polling wave's rows in LDS) have landed
+    if (!pollw) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    // the polling wave's ring registers are otherwise unused: its rows land there
+    if (pollw) {
+#pragma unroll
+      for (int l = 0; l < B; ++l)
+#pragma unroll
+        for (int c = 0; c < R; ++c) cur[l][c] = pbuf[pb][pw][l][c][lane];
+    }
+    auto& xl = cur;
+#pragma unroll
+    for (int l = 0; l < B; ++l)
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+        if (lim[c] < VEC) xl[l][c] = mask_chunk<S>(xl[l][c], lim[c]);
+    float p[NV];
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(xl[l][c], i), e[c][i], acc);
+      p[l] = acc;
+    }
+    {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc = fmaf(e[c][i], e[c][i], acc);
+      p[B] = acc;
+    }
+    bool aborting = false;
+    if (bi == 0 && wg == 0 && tid == 0 && load_flag(&A.ctl[CTL_ABORT]) != 0) {
+      p[B] = __int_as_float(0x7fc00000);
+      aborting = true;
+    }
+    const int par = (int)(seq & 1u);
+#pragma unroll
+    for (int l = 0; l < NV; ++l) {
+      const float v = wave_sum(p[l]);
+      if (lane == 0) red[par][wave][l] = v;
+    }
+    __syncthreads();
+    uint64_t* slot_base = A.slots + (int64_t)par * NV * A.P;
+    if (!pollw) {
+      // next block: columns in flight during the exchange (the block after the
+      // last one of the launch is a valid block, requested and never used)
+      int pbi = bi + 1;
+      if (pbi >= nb) pbi -= nb;
+      load_block(pf, pbi, pb ^ 1);
+      cpf.load(A.rdn, A.gram, pbi, lane);
+    } else {
+      if (pw == 0 && lane < NV) {
+        float sacc = 0.f;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) sacc += red[par][w][lane];
+        publish(slot_base + (int64_t)lane * A.P + wg, seq, sacc);
+      }
+      if (A.poll_delay) {
+        const uint64_t t0d = now_ticks();
+        while (now_ticks() - t0d < A.poll_delay) __builtin_amdgcn_s_sleep(2);
+      }
+      // polling wave pw reads chunks pw*CPP .. of 64 workgroups: word
+      // (l, c*64 + lane); lanes past the last workgroup read a valid word
+      const int ncn = (A.P + WAVE - 1) / WAVE;
+      uint64_t w[NV][CPP];
+#pragma unroll
+      for (int k = 0; k < CPP; ++k) {
+        const int c = pw * CPP + k;
+        const int idx = c * WAVE + lane;
+        const bool live = c < ncn && idx < A.P;
+#pragma unroll
+        for (int l = 0; l < NV; ++l) w[l][k] = peek(slot_base + (int64_t)l * A.P + (live ? idx : 0));
+      }
+#pragma unroll
+      for (int k = 0; k < CPP; ++k) {
+        const int c = pw * CPP + k;
+        const int idx = c * WAVE + lane;
+        const bool live = c < ncn && idx < A.P;
+#pragma unroll
+        for (int l = 0; l < NV; ++l)
+          if (!live) w[l][k] = (uint64_t)seq << 32;
+      }
+      uint64_t tstart = 0;
+      bool timed_out = false;
+      for (int spin = 0;; ++spin) {
+        bool ready = true;
+#pragma unroll
+        for (int l = 0; l < NV; ++l)
+#pragma unroll
+          for (int k = 0; k < CPP; ++k) ready = ready && ((uint32_t)(w[l][k] >> 32) == seq);
+        if (ready) break;
+        if (spin == 0) tstart = now_ticks();
+        else if (now_ticks() - tstart > A.timeout_ticks) {
+          timed_out = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int k = 0; k < CPP; ++k) {
+          const int idx = (pw * CPP + k) * WAVE + lane;
+#pragma unroll
+          for (int l = 0; l < NV; ++l)
+            if ((uint32_t)(w[l][k] >> 32) != seq) w[l][k] = peek(slot_base + (int64_t)l * A.P + idx);
+        }
+      }
+      // fixed order: per lane over its chunks, across the lanes, then over
+      // the polling waves
+#pragma unroll
+      for (int l = 0; l < NV; ++l) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < CPP; ++k) {
+          const int c = pw * CPP + k;
+          const int idx = c * WAVE + lane;
+          acc += (c < ncn && idx < A.P) ? (double)__uint_as_float((uint32_t)w[l][k]) : 0.0;
+        }
+        const double tl = wave_sum(acc);
+        if (lane == 0) tpart[pw][l] = tl;
+      }
+      if (timed_out && lane == 0) sflag = 1;
+      int pbi = bi + 1;
+      if (pbi >= nb) pbi -= nb;
+      cpf.load(A.rdn, A.gram, pbi, lane);
+    }
+    __syncthreads();
+    if (sflag) {
+      if (tid == 0) store_flag(&A.ctl[CTL_ERR], ERR_TIMEOUT);
+      return true;
+    }
+    double tot[NV];
+#pragma unroll
+    for (int l = 0; l < NV; ++l) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < NPW; ++q) acc += tpart[q][l];
+      tot[l] = uniform_f64(acc);
+    }
+
+    const double nrm2 = tot[B];
+    const double nrm = sqrt(nrm2);
+    if (!(nrm2 <= DBL_MAX)) {
+      if (wg == 0 && tid == 0) store_flag(&A.ctl[CTL_ERR], aborting ? ERR_ABORTED : ERR_NONFINITE);
+      finalize(sdone, false, (int64_t)sdone * n + j0, nrm2);
+      return true;
+    }
+    if (bi == 0) {
+      if (wg == 0 && tid == 0) { A.hist[sdone] = nrm; A.fstat[1] = nrm; }
+      bool stop = false, conv = false;
+      if (A.stop != STOP_NONE && nrm2 == 0.0) stop = conv = true;
+      else if (A.stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < A.tol * nrm) stop = conv = true;
+      else if (A.stop == STOP_REL_RESID && nrm < A.tol * ynorm) stop = conv = true;
+      if (!stop && sdone >= A.max_sweeps) stop = true;
+      prev_norm = nrm;
+      if (stop) { finalize(sdone, conv, (int64_t)sdone * n, nrm2); return true; }
+    } else if (A.check_cols > 0 && A.stop == STOP_REL_RESID) {
+      const int64_t cols = (int64_t)sdone * n + j0;
+      if (cols % A.check_cols == 0 && (nrm2 == 0.0 || nrm < A.tol * ynorm)) {
+        finalize(sdone, true, cols, nrm2);
+        return true;
+      }
+    }
+    double da[B];
+    forward_substitute<B>(tot, ccur, da);
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      const float f = (float)da[l];
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) e[c][i] = fmaf(-f, S::get(xl[l][c], i), e[c][i]);
+    }
+    if (tid < B) {
+      const int64_t j = j0 + tid;
+      if (j < n && (int)(j % A.P) == wg) {
+        double d = 0.0;
+#pragma unroll
+        for (int l = 0; l < B; ++l) if (tid == l) d = da[l];
+        (void)__hip_atomic_fetch_add(&A.a64[j], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    bi = nbi;
+    if (bi == 0) ++sdone;
+    ++seq;
+    return false;
+  };
+
+  if (nblocks > 0) {
+    if (!pollw) load_block(x0, bi, 0);
+    c0.load(A.rdn, A.gram, bi, lane);
+  }
+  for (int64_t k = 0; k < nblocks;) {
+    if (step(x0, x1, c0, c1, k)) break;
+    if (++k >= nblocks) break;
+    if (step(x1, x0, c1, c0, k)) break;
+    ++k;
+  }
+  // no direct-to-LDS load may still be in flight when the workgroup ends
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #pragma unroll
   for (int c = 0; c < R; ++c)
 #pragma unroll
@@ -1247,8 +1597,12 @@ struct Variant {
   {T, R, B, HPSCD_IS_BF16_##S, true, 10 + D, reinterpret_cast<const void*>(&k_sweep_ws<S, T, R, B, D>), T + WAVE},
 #define HPSCD_PENTRY(S, T, R, B) \
   {T, R, B, HPSCD_IS_BF16_##S, true, 4, reinterpret_cast<const void*>(&k_sweep_pipe<S, T, R, B>), T},
+#define HPSCD_PX_VARIANTS(X_) \
+  X_(F32, 512, 2, 8, 2) X_(F32, 512, 2, 4, 1) X_(F32, 256, 4, 4, 1) X_(F32, 256, 4, 8, 2) X_(BF16, 512, 1, 8, 2)
+#define HPSCD_XENTRY(S, T, R, B, NPW) \
+  {T, R, B, HPSCD_IS_BF16_##S, true, 5, reinterpret_cast<const void*>(&k_sweep_px<S, T, R, B, NPW>), T},
 static const Variant kVariants[] = {HPSCD_SWEEP_VARIANTS(HPSCD_ENTRY) HPSCD_PIPE_VARIANTS(HPSCD_PENTRY)
-                                        HPSCD_WS_VARIANTS(HPSCD_WENTRY)};
+                                        HPSCD_WS_VARIANTS(HPSCD_WENTRY) HPSCD_PX_VARIANTS(HPSCD_XENTRY)};
 
 // The deepest prefetch ring built for the shape (D = 0: any).
 static const Variant* find_variant(int T, int R, int B, bool bf16, bool grid, int D = 0) {
@@ -1266,7 +1620,7 @@ bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid, int D) {
 int sweep_max_workgroups(int T, int R, int B, bool bf16, bool grid, int D) {
   const Variant* v = find_variant(T, R, B, bf16, grid, D);
   if (!v) return 0;
-  return v->D >= 10 ? 256 : 512;
+  return (v->D >= 10 || v->D == 5) ? 256 : 512;
 }
 
 int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid, int D) {

@@ -58,7 +58,8 @@ class Info(ctypes.Structure):
                 ("zero_cols", ctypes.c_int64), ("final_norm", ctypes.c_double),
                 ("final_rel_resid", ctypes.c_double), ("y_norm", ctypes.c_double),
                 ("block_used", ctypes.c_int32), ("team_wgs", ctypes.c_int32), ("team_threads", ctypes.c_int32),
-                ("refreshes", ctypes.c_int32), ("sweep_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+                ("refreshes", ctypes.c_int32), ("sweep_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("kernel_kind", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

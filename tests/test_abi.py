@@ -41,9 +41,9 @@ def test_struct_layouts_match_header(hp):
 #include <stddef.h>
 #include "hpscd.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(hpscd_opts), sizeof(hpscd_info), sizeof(hpscd_sys),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hpscd_opts), sizeof(hpscd_info), sizeof(hpscd_sys),
          offsetof(hpscd_opts, tol), offsetof(hpscd_info, final_norm), offsetof(hpscd_info, total_ms),
-         offsetof(hpscd_sys, tol));
+         offsetof(hpscd_sys, tol), offsetof(hpscd_info, kernel_kind));
   return 0;
 }
 '''
@@ -54,7 +54,8 @@ int main(void) {
         subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     assert got == [ctypes.sizeof(hp.Opts), ctypes.sizeof(hp.Info), ctypes.sizeof(hp.Sys),
-                   hp.Opts.tol.offset, hp.Info.final_norm.offset, hp.Info.total_ms.offset, hp.Sys.tol.offset]
+                   hp.Opts.tol.offset, hp.Info.final_norm.offset, hp.Info.total_ms.offset, hp.Sys.tol.offset,
+                   hp.Info.kernel_kind.offset]
 
 
 def test_version(hp):

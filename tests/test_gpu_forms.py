@@ -241,3 +241,18 @@ def test_batched_size_boundaries(lib):
         ao = b.table[i, 5]
         assert rel(a[ao: ao + s.n], ref.a) <= 1e-5, sizes[i]
         assert np.all(np.abs(r.hist[i] - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0]), sizes[i]
+
+
+def test_bf16_polling_wave_kernel(lib):
+    """The storage form through the polling-wave grid kernel (kind 5), with
+    refreshes between launch segments, against the oracle of the form."""
+    s = gen.tall_large(m=150_000, n=40, seed=23)
+    X32 = dev(s.Xt)
+    Xb = lib.convert_bf16(X32)
+    say("bf16 px")
+    r = lib.solve_bf16(Xb, X32, dev(s.y), max_sweeps=4, refresh_cols=40, block=8, depth=5, team_threads=512,
+                       flags=lib.F_FORCE_GRID)
+    ref = oracle.solve_bf16_refresh(s.Xt, s.y, s.m, max_sweeps=4, refresh_cols=40)
+    assert r.info["refreshes"] == ref.refreshes
+    assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
+    assert np.all(np.abs(np.asarray(r.hist) - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0])

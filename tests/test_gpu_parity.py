@@ -220,11 +220,12 @@ def test_residual_f64(lib):
 
 # ------------------------------------------------------------ pipelined grid
 
-@pytest.mark.parametrize("block,kind", [(2, 4), (4, 4), (4, 12), (4, 13), (8, 12)])
+@pytest.mark.parametrize("block,kind", [(2, 4), (4, 4), (4, 12), (4, 13), (8, 12), (8, 5), (4, 5)])
 def test_grid_kernel_kinds_match_oracle(lib, block, kind):
     """Every grid kernel kind (pipelined reductions with the cross-block Gram
-    correction; warp-specialised with a two- or three-block ring) produces the
-    iterates of Algorithm 1 (n not a multiple of the block, ragged rows)."""
+    correction; warp-specialised with a two- or three-block ring; polling
+    waves fed through LDS) produces the iterates of Algorithm 1 (n not a
+    multiple of the block, ragged rows)."""
     s = gen.tall_large(m=300_003, n=37, seed=13, pad=np.nan)
     say("grid kind", block, kind)
     r, ref = check(lib, s, 6, block=block, depth=kind)
@@ -245,3 +246,22 @@ def test_pipelined_grid_warm_start(lib):
     a0 = np.random.default_rng(2).standard_normal(s.n).astype(np.float32)
     say("pipelined warm")
     check(lib, s, 3, a0=a0, block=4, depth=4)
+
+
+@pytest.mark.parametrize("team_threads", [256, 512])
+def test_polling_wave_kernel_shapes(lib, team_threads):
+    """The polling-wave kernel with one (512 x 2, block 4) or two (256 x 4,
+    block 8) polling waves, whose rows reach them through LDS, against the
+    oracle on a ragged system with a warm start and the relative-change stop."""
+    s = gen.tall_large(m=200_001, n=45, seed=21, pad=np.nan)
+    block = 8 if team_threads == 256 else 4
+    say("px", team_threads, block)
+    rng = np.random.default_rng(3)
+    a0 = rng.standard_normal(s.n).astype(np.float32)
+    r = lib.solve(dev(s.Xt), dev(s.y), dev(a0), max_sweeps=30, stop=lib.STOP_REL_CHANGE, tol=1e-5, block=block,
+                  depth=5, team_threads=team_threads, flags=lib.F_FORCE_GRID)
+    ref = oracle.solve(s.Xt, s.y, s.m, a0=a0.astype(np.float64), max_sweeps=30, stop=oracle.STOP_REL_CHANGE, tol=1e-5)
+    assert abs(r.info["sweeps_done"] - ref.sweeps) <= 1
+    ref_eq = oracle.solve(s.Xt, s.y, s.m, a0=a0.astype(np.float64), max_sweeps=r.info["sweeps_done"])
+    assert rel(r.a.cpu().numpy(), ref_eq.a) <= 1e-5
+    assert r.info["team_threads"] == team_threads and r.info["team_wgs"] > 1
