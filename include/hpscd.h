@@ -74,8 +74,10 @@ typedef struct {
   int32_t depth;        /* kernel kind; 0 = library choice.  2, 3: prefetch ring of 2 or 3 blocks;
                            4: pipelined grid kernel, or a 4-block ring for one workgroup;
                            5: grid kernel whose polling waves never wait behind column loads
-                           (their rows arrive through LDS); 12, 13: grid kernel with a
-                           dedicated reduction wave, ring of 2 or 3 */
+                           (their rows arrive through LDS); 6, 7: grid kernel with one polling
+                           wave and a ring of 2 or 3 column blocks requested as soon as a
+                           buffer frees; 12, 13: grid kernel with a dedicated reduction wave,
+                           ring of 2 or 3 */
 } hpscd_opts;
 
 typedef struct {

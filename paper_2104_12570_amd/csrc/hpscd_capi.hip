@@ -133,9 +133,9 @@ hpscd_status validate_opts(const hpscd_opts* o) {
   if (o->refresh_cols < 0) return fail(HPSCD_EINVAL, "refresh_cols must be >= 0");
   if (o->block != 0 && o->block != 1 && o->block != 2 && o->block != 4 && o->block != 8)
     return fail(HPSCD_EINVAL, "block must be 0, 1, 2, 4 or 8 (got %d)", o->block);
-  if (o->depth != 0 && o->depth != 2 && o->depth != 3 && o->depth != 4 && o->depth != 5 && o->depth != 12 &&
-      o->depth != 13)
-    return fail(HPSCD_EINVAL, "depth (kernel kind) must be 0, 2, 3, 4, 5, 12 or 13 (got %d)", o->depth);
+  if (o->depth != 0 && o->depth != 2 && o->depth != 3 && o->depth != 4 && o->depth != 5 && o->depth != 6 &&
+      o->depth != 7 && o->depth != 12 && o->depth != 13)
+    return fail(HPSCD_EINVAL, "depth (kernel kind) must be 0, 2, 3, 4, 5, 6, 7, 12 or 13 (got %d)", o->depth);
   if ((o->flags & HPSCD_F_FORCE_GRID) && (o->flags & HPSCD_F_FORCE_WG))
     return fail(HPSCD_EINVAL, "FORCE_GRID and FORCE_WG are exclusive");
   if ((int64_t)o->max_sweeps + 1 > (int64_t)1 << 30) return fail(HPSCD_EINVAL, "max_sweeps too large");
@@ -176,10 +176,14 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
     else shapes = {{256, 2}, {256, 4}};
   }
   const int want = o->block > 0 ? o->block : (grid ? 8 : 4);
-  const int64_t need_n = o->refresh_cols > 0 ? n : 0;
+  // Stop checks and refreshes fall at block starts, counted in column steps
+  // from the start of the solve: the block must divide n for those to land
+  // on every multiple of check_cols (refresh_cols).
+  const bool checks = o->check_cols > 0 && o->stop == HPSCD_STOP_REL_RESID;
+  const int64_t need_n = (o->refresh_cols > 0 || checks) ? n : 0;
   int B = pick_block(want, {o->check_cols, o->refresh_cols, need_n});
   if (o->block > 0 && B != o->block)
-    return fail(HPSCD_EINVAL, "block %d must divide check_cols, refresh_cols and (with refresh) n", o->block);
+    return fail(HPSCD_EINVAL, "block %d must divide check_cols, refresh_cols and (with either) n", o->block);
   if (o->team_threads > 0) {
     std::vector<std::pair<int, int>> keep;
     for (int R : {1, 2, 4}) keep.push_back({o->team_threads, R});
@@ -228,7 +232,7 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
 // system and on 64k..500k-row systems).
 uint32_t poll_delay_ticks(const Plan& pl) {
   if (!pl.grid) return 0;
-  if (pl.D == 5) return (uint32_t)std::min(240.0, 80.0 + 0.6 * pl.P);
+  if (pl.D == 5 || pl.D == 6 || pl.D == 7) return (uint32_t)std::min(240.0, 80.0 + 0.6 * pl.P);
   if (pl.D == 2 || pl.D == 3) return (uint32_t)std::min(160.0, 0.65 * pl.P);
   return 0;
 }

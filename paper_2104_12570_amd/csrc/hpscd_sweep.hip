@@ -740,6 +740,496 @@ __global__ void __launch_bounds__(T) k_sweep_px(SolveArgs A) {
 }
 
 // --------------------------------------------------------------------------
+// Grid kernel with a polling wave and a ring of D column blocks.
+//
+// The waves of a workgroup split into NH = NW - 1 streaming waves and one
+// polling wave that run separate loops, meeting at the same three barriers
+// per block, so each loop holds only its own registers:
+//  * a streaming wave keeps a ring of D register blocks.  It requests a
+//    block as soon as the buffer that will hold it is free (right after the
+//    axpy of the block D steps earlier), so the next D - 1 blocks are in
+//    flight while the current one is reduced: a block has D - 1 steps to
+//    arrive.  It also loads a share of the polling wave's rows and, once
+//    they have landed, copies them to LDS (plain loads: direct-to-LDS loads
+//    of those rows cost the column stream about a third of its rate).
+//    Column loads are its only vector memory operations, so it waits for the
+//    block it is about to use with an explicit count of the operations
+//    issued after that block (its share of the polling wave's rows is taken
+//    at its minimum: the wait may be slightly longer, never shorter).
+//  * the polling wave issues no column loads, so its polls of the exchange
+//    words never queue behind column data.  It takes its rows from LDS,
+//    publishes the workgroup's partial sums, sums the other workgroups',
+//    runs the stop tests and the forward substitution, and hands the
+//    block's steps da to the streaming waves through LDS.
+// The barriers order LDS only (an LDS wait and s_barrier): a barrier with
+// memory fences would also wait for the column loads in flight.
+// Arithmetic, reduction order and stop logic are those of k_sweep.
+__device__ inline void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// Keeps the memory operations before it before it and those after it after
+// it, both in the compiler's IR and in its instruction scheduling.
+__device__ inline void pin_order() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int N>
+__device__ inline void wait_vm_at_most() {
+  static_assert(N >= 0 && N <= 63, "vmcnt range");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+template <class S, int T, int R, int B, int D>
+__global__ void __launch_bounds__(T) k_sweep_pe(SolveArgs A) {
+  using raw = typename S::raw_t;
+  constexpr int VEC = S::VEC;
+  constexpr int NW = T / WAVE;
+  constexpr int NV = B + 1;
+  constexpr int NH = NW - 1;                         // waves that stream columns
+  constexpr int MAXC = 4;                            // up to 256 workgroups
+  constexpr int U = B * R;                           // chunks of the poller's rows per block
+  constexpr int UPW = (U + NH - 1) / NH;             // ... loaded by one streaming wave, at most
+  constexpr int UMIN = U / NH;                       // ... and at least
+  constexpr int OPS_MIN = B * R + UMIN;              // vector memory operations per block and streaming wave
+  constexpr int WAIT_N = (D - 1) * OPS_MIN < 63 ? (D - 1) * OPS_MIN : 63;
+  static_assert(NW >= 2 && (D == 2 || D == 3), "wave split, ring depth");
+  using pbuf_t = raw[B][R][WAVE];
+  constexpr int NG = B * (B - 1) / 2;
+  constexpr int MAXCOEF = 8192;  // coefficient table held in LDS up to this many doubles
+  constexpr int MAXOWN = 512;    // a_j of the columns this workgroup owns, held in LDS up to this many
+  __shared__ float red[NW][NV];
+  __shared__ pbuf_t pbuf;  // the polling wave's rows of the current block
+  __shared__ double sda[B];
+  __shared__ int sstop;
+  __shared__ double scoef[MAXCOEF];
+  __shared__ double sown[MAXOWN];
+
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
+  const bool pollw = wave == NH;
+  const int wg = (int)blockIdx.x;
+  const int64_t m = A.m, n = A.n;
+  const int nb = (int)((n + B - 1) / B);
+  if (A.ctl[CTL_NONFINITE] != 0 || A.ctl[CTL_DONE] != 0) return;
+
+  float e[R][VEC];
+  int lim[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    const int64_t r0 = (int64_t)wg * (T * R * VEC) + (int64_t)VEC * (tid + T * c);
+    const int64_t left = m - r0;
+    lim[c] = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? A.e0[r0 + i] : 0.f;
+  }
+  const int64_t nblocks = A.blk_end - A.blk_begin;
+  const int64_t col_bytes = A.ldx * (int64_t)(16 / VEC);
+  // Rows past m: a chunk with no valid row is read from the workgroup's first
+  // chunk instead (finite data; its residual is held at zero), and the one
+  // chunk of the system that straddles m is masked element by element.
+  const bool ragged = (int64_t)(wg + 1) * (T * R * VEC) > m;  // the workgroup holding the last rows
+  bool straddle[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) straddle[c] = __ballot(lim[c] > 0 && lim[c] < VEC) != 0;
+
+  // Partial sums of the block (B dots against the block-start residual and
+  // ||e||^2) of this wave's rows, to LDS.
+  auto partials = [&](raw (&xl)[B][R]) {
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+      if (straddle[c]) {  // wave-uniform
+#pragma unroll
+        for (int l = 0; l < B; ++l)
+          if (lim[c] > 0 && lim[c] < VEC) xl[l][c] = mask_chunk<S>(xl[l][c], lim[c]);
+      }
+    float p[NV];
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(xl[l][c], i), e[c][i], acc);
+      p[l] = acc;
+    }
+    {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc = fmaf(e[c][i], e[c][i], acc);
+      p[B] = acc;
+    }
+#pragma unroll
+    for (int l = 0; l < NV; ++l) {
+      const float v = wave_sum(p[l]);
+      if (lane == 0) red[wave][l] = v;
+    }
+  };
+  auto axpy = [&](const raw (&xl)[B][R], const double (&da)[B]) {
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      const float f = (float)da[l];
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) e[c][i] = fmaf(-f, S::get(xl[l][c], i), e[c][i]);
+    }
+    if (ragged) {
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? e[c][i] : 0.f;
+    }
+  };
+
+  if (!pollw) {
+    // ------------------------------------------------------ streaming waves
+    const int64_t wg_row0 = (int64_t)wg * (T * R * VEC);
+    uint32_t boff[R];  // own rows (a chunk with no valid row reads the workgroup's first chunk)
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+      boff[c] = (uint32_t)((lim[c] > 0 ? wg_row0 + (int64_t)VEC * (tid + T * c) : wg_row0) * (16 / VEC));
+    uint32_t boffp[R];  // the polling wave's rows, lane for lane (likewise)
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      const int64_t r0 = wg_row0 + (int64_t)VEC * (NH * WAVE + lane + T * c);
+      boffp[c] = (uint32_t)((r0 < m ? r0 : wg_row0) * (16 / VEC));
+    }
+    raw x0[B][R], x1[B][R], x2[D == 3 ? B : 1][R];
+    raw q0[UPW], q1[UPW], q2[D == 3 ? UPW : 1];  // this wave's share of the poller's rows
+    int bi = (int)(A.blk_begin % nb);
+    const int sw = wave < NH ? wave : 0;  // this streaming wave (bounded for the compiler)
+    // Request block rb: own columns, then chunks u = sw, sw + NH, ... (column
+    // u / R, chunk u % R) of the polling wave's rows.  Loads past the last
+    // column return zero; rows past m are masked before use.
+    auto request = [&](raw (&x)[B][R], raw (&q)[UPW], int rb) {
+      const int j0 = rb * B;
+      const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
+      const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
+      const uint32_t nrec = span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<char*>(reinterpret_cast<const char*>(A.X) + (int64_t)j0 * col_bytes), 0, (int)nrec, 0x00020000);
+#pragma unroll
+      for (int l = 0; l < B; ++l)
+#pragma unroll
+        for (int c = 0; c < R; ++c)
+          x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
+#pragma unroll
+      for (int i = 0; i < UPW; ++i) {
+        const int u = sw + NH * i;
+        if (i < UMIN || u < U) {  // (the first UMIN are unconditional: the compiler counts them)
+          const int l = u / R, c = u % R;  // wave-uniform
+          uint32_t vo = boffp[0];
+#pragma unroll
+          for (int cc = 1; cc < R; ++cc)
+            if (c == cc) vo = boffp[cc];
+          q[i] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)vo, (int)(l * col_bytes), 0));
+        }
+      }
+    };
+    // (after the block has landed) this wave's share of the poller's rows to LDS
+    auto share = [&](const raw (&q)[UPW]) {
+#pragma unroll
+      for (int i = 0; i < UPW; ++i) {
+        const int u = sw + NH * i;
+        if (i < UMIN || u < U) pbuf[u / R][u % R][lane] = q[i];
+      }
+    };
+    auto ahead = [&](int d) {
+      int r = bi + d;
+      while (r >= nb) r -= nb;
+      return r;
+    };
+    // A step that is not taken (the solve has stopped, or the launch's
+    // blocks are done) still requests its next block: every path to the top
+    // of the loop then issues the same loads in the same order, which keeps
+    // the compiler's own waits for the ring registers exact.  Blocks
+    // requested after the last one used are valid and never read.
+    bool stopped = false;
+    auto step = [&](raw (&cur)[B][R], raw (&q)[UPW], int64_t k) {
+      const int rb = ahead(D);  // the block this buffer holds next
+      if (!stopped && k < nblocks) {
+        // this block (own rows and the share of the poller's rows) has
+        // landed; the next blocks' loads stay in flight
+        wait_vm_at_most<WAIT_N>();
+        share(q);
+        lds_barrier();
+        partials(cur);
+        lds_barrier();
+        // (the polling wave exchanges the partial sums with the grid)
+        lds_barrier();
+        if (__builtin_amdgcn_readfirstlane(sstop)) {
+          stopped = true;
+        } else {
+          double da[B];
+#pragma unroll
+          for (int l = 0; l < B; ++l) da[l] = sda[l];
+          axpy(cur, da);
+          bi = (bi + 1 == nb) ? 0 : bi + 1;
+        }
+      }
+      // the buffer is free: request the block D ahead
+      request(cur, q, rb);
+      pin_order();  // issued early is the point
+    };
+    if (nblocks > 0) {
+      // The loads in flight at the top of the loop are, in issue order,
+      // blocks b .. b+D-1, on entry as on every later turn.
+      pin_order();
+      request(x0, q0, bi);
+      pin_order();
+      request(x1, q1, ahead(1));
+      pin_order();
+      if constexpr (D == 3) {
+        request(x2, q2, ahead(2));
+        pin_order();
+        for (int64_t k = 0;; k += 3) {
+          step(x0, q0, k);
+          step(x1, q1, k + 1);
+          step(x2, q2, k + 2);
+          if (stopped || k + 3 >= nblocks) break;
+        }
+      } else {
+        for (int64_t k = 0;; k += 2) {
+          step(x0, q0, k);
+          step(x1, q1, k + 1);
+          if (stopped || k + 2 >= nblocks) break;
+        }
+      }
+    }
+    // (the loads of the blocks requested past the end are left to land)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  } else {
+    // --------------------------------------------------------- polling wave
+    // Its vector memory operations (exchange words, coefficients) go ahead of
+    // the streaming waves' queued column loads when both wait to issue.
+    __builtin_amdgcn_s_setprio(3);
+    const bool leader = wg == 0 && lane == 0;  // writes the solve's control words
+    double prev_norm = A.fstat[1];
+    const double ynorm = sqrt(*A.ynorm2);
+    int bi = (int)(A.blk_begin % nb);
+    int sdone = (int)(A.blk_begin / nb);
+    uint32_t seq = (uint32_t)(A.blk_begin + 1);
+    bool aborting = false;
+    Coef<B> c0, c1, c2;
+    // The block coefficients and this workgroup's a_j (columns j = wg + i*P)
+    // are kept in LDS when they fit, so that the step after the exchange
+    // issues no vector memory operation: one issued while the streaming
+    // waves' column loads wait to issue would queue behind them.
+    const int64_t nrdn = (int64_t)nb * B, ncoef = nrdn + (int64_t)nb * NG;
+    const bool coef_lds = ncoef <= MAXCOEF;
+    if (coef_lds) {
+      for (int64_t i = lane; i < nrdn; i += WAVE) scoef[i] = A.rdn[i];
+      for (int64_t i = lane; i < ncoef - nrdn; i += WAVE) scoef[nrdn + i] = A.gram[i];
+    }
+    const int64_t nown = (n - wg + A.P - 1) / A.P;
+    const bool own_lds = nown <= MAXOWN;
+    if (own_lds)
+      for (int64_t i = lane; i < nown; i += WAVE) sown[i] = A.a64[wg + i * A.P];
+    auto load_coef = [&](Coef<B>& cf, int rb) {
+      if (coef_lds) cf.load(scoef, scoef + nrdn, rb, lane);
+      else cf.load(A.rdn, A.gram, rb, lane);
+    };
+    auto finalize = [&](int sd, bool conv, int64_t cols, double nrm2) {
+      if (leader) {
+        A.ctl[CTL_SWEEPS] = sd;
+        A.ctl[CTL_CONVERGED] = conv ? 1 : 0;
+        A.ctl[CTL_DONE] = 1;
+        A.ctl64[C64_COLS] = cols;
+        A.fstat[0] = nrm2;
+      }
+    };
+    // The grid totals of the block, the stop tests, the block's steps da.
+    // True when the solve ends here.
+    auto conclude = [&](const double (&tot)[NV], bool timed_out, const Coef<B>& cf, double (&da)[B]) -> bool {
+      const int j0 = bi * B;
+      if (timed_out) {
+        if (leader) store_flag(&A.ctl[CTL_ERR], ERR_TIMEOUT);
+        return true;
+      }
+      const double nrm2 = tot[B];
+      const double nrm = sqrt(nrm2);
+      if (!(nrm2 <= DBL_MAX)) {
+        if (leader) store_flag(&A.ctl[CTL_ERR], aborting ? ERR_ABORTED : ERR_NONFINITE);
+        finalize(sdone, false, (int64_t)sdone * n + j0, nrm2);
+        return true;
+      }
+      if (bi == 0) {
+        if (leader) { A.hist[sdone] = nrm; A.fstat[1] = nrm; }
+        bool stop = false, conv = false;
+        if (A.stop != STOP_NONE && nrm2 == 0.0) stop = conv = true;
+        else if (A.stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < A.tol * nrm) stop = conv = true;
+        else if (A.stop == STOP_REL_RESID && nrm < A.tol * ynorm) stop = conv = true;
+        if (!stop && sdone >= A.max_sweeps) stop = true;
+        prev_norm = nrm;
+        if (stop) { finalize(sdone, conv, (int64_t)sdone * n, nrm2); return true; }
+      } else if (A.check_cols > 0 && A.stop == STOP_REL_RESID) {
+        const int64_t cols = (int64_t)sdone * n + j0;
+        if (cols % A.check_cols == 0 && (nrm2 == 0.0 || nrm < A.tol * ynorm)) {
+          finalize(sdone, true, cols, nrm2);
+          return true;
+        }
+      }
+      forward_substitute<B>(tot, cf, da);
+      return false;
+    };
+    bool stopped = false;
+    auto step = [&](Coef<B>& ccur, int64_t k) {
+      if (stopped || k >= nblocks) return;
+      lds_barrier();
+      raw xl[B][R];
+#pragma unroll
+      for (int l = 0; l < B; ++l)
+#pragma unroll
+        for (int c = 0; c < R; ++c) xl[l][c] = pbuf[l][c][lane];
+      partials(xl);
+      lds_barrier();
+      const uint64_t* slot_base = A.slots + (int64_t)(seq & 1u) * NV * A.P;
+      bool injected = false;
+      if (lane < NV) {
+        float sacc = 0.f;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) sacc += red[w][lane];
+        // a cancel request rides the norm of a sweep's first block as a NaN
+        if (lane == B && bi == 0 && wg == 0 && load_flag(&A.ctl[CTL_ABORT]) != 0) {
+          sacc = __int_as_float(0x7fc00000);
+          injected = true;
+        }
+        publish(const_cast<uint64_t*>(slot_base) + (int64_t)lane * A.P + wg, seq, sacc);
+      }
+      aborting = __ballot(injected) != 0;
+      if (A.poll_delay) {
+        const uint64_t t0d = now_ticks();
+        while (now_ticks() - t0d < A.poll_delay) __builtin_amdgcn_s_sleep(2);
+      }
+      // chunk c of 64 workgroups: word (l, c*64 + lane); lanes past the last
+      // workgroup read a valid word and count as ready
+      const int ncn = (A.P + WAVE - 1) / WAVE;
+      uint64_t w[NV][MAXC];
+#pragma unroll
+      for (int c = 0; c < MAXC; ++c) {
+        const int idx = c * WAVE + lane;
+        const bool live = c < ncn && idx < A.P;
+#pragma unroll
+        for (int l = 0; l < NV; ++l) w[l][c] = peek(slot_base + (int64_t)l * A.P + (live ? idx : 0));
+      }
+#pragma unroll
+      for (int c = 0; c < MAXC; ++c) {
+        const int idx = c * WAVE + lane;
+        const bool live = c < ncn && idx < A.P;
+#pragma unroll
+        for (int l = 0; l < NV; ++l)
+          if (!live) w[l][c] = (uint64_t)seq << 32;
+      }
+      uint64_t tstart = 0;
+      bool timed_out = false;
+      for (int spin = 0;; ++spin) {
+        bool ready = true;
+#pragma unroll
+        for (int l = 0; l < NV; ++l)
+#pragma unroll
+          for (int c = 0; c < MAXC; ++c) ready = ready && ((uint32_t)(w[l][c] >> 32) == seq);
+        if (ready) break;
+        if (spin == 0) tstart = now_ticks();
+        else if (now_ticks() - tstart > A.timeout_ticks) {
+          timed_out = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+          const int idx = c * WAVE + lane;
+#pragma unroll
+          for (int l = 0; l < NV; ++l)
+            if ((uint32_t)(w[l][c] >> 32) != seq) w[l][c] = peek(slot_base + (int64_t)l * A.P + idx);
+        }
+      }
+      // fixed order: per lane over its chunks, then across the lanes
+      double tot[NV];
+#pragma unroll
+      for (int l = 0; l < NV; ++l) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+          const int idx = c * WAVE + lane;
+          acc += (c < ncn && idx < A.P) ? (double)__uint_as_float((uint32_t)w[l][c]) : 0.0;
+        }
+        tot[l] = uniform_f64(wave_sum(acc));
+      }
+      double da[B];
+      const bool stop = conclude(tot, __ballot(timed_out) != 0, ccur, da);
+      if (lane == 0) {
+        sstop = stop ? 1 : 0;
+#pragma unroll
+        for (int l = 0; l < B; ++l) sda[l] = da[l];
+      }
+      lds_barrier();
+      if (stop) {
+        stopped = true;
+        return;
+      }
+      axpy(xl, da);
+      // a_j of this block: one lane per column, columns dealt out over the
+      // workgroups
+      if (lane < B) {
+        const int64_t j = (int64_t)bi * B + lane;
+        if (j < n && (int)(j % A.P) == wg) {
+          double d = 0.0;
+#pragma unroll
+          for (int l = 0; l < B; ++l) if (lane == l) d = da[l];
+          if (own_lds) sown[(j - wg) / A.P] += d;
+          else (void)__hip_atomic_fetch_add(&A.a64[j], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      int rb = bi + D;
+      while (rb >= nb) rb -= nb;
+      load_coef(ccur, rb);
+      bi = (bi + 1 == nb) ? 0 : bi + 1;
+      if (bi == 0) ++sdone;
+      ++seq;
+    };
+    if (nblocks > 0) {
+      auto at = [&](int d) {
+        int r = bi + d;
+        while (r >= nb) r -= nb;
+        return r;
+      };
+      load_coef(c0, bi);
+      load_coef(c1, at(1));
+      if constexpr (D == 3) {
+        load_coef(c2, at(2));
+        for (int64_t k = 0;; k += 3) {
+          step(c0, k);
+          step(c1, k + 1);
+          step(c2, k + 2);
+          if (stopped || k + 3 >= nblocks) break;
+        }
+      } else {
+        for (int64_t k = 0;; k += 2) {
+          step(c0, k);
+          step(c1, k + 1);
+          if (stopped || k + 2 >= nblocks) break;
+        }
+      }
+    }
+    if (own_lds)
+      for (int64_t i = lane; i < nown; i += WAVE) A.a64[wg + i * A.P] = sown[i];
+  }
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    const int64_t r0 = (int64_t)wg * (T * R * VEC) + (int64_t)VEC * (tid + T * c);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i)
+      if (i < lim[c]) A.e_out[r0 + i] = e[c][i];
+  }
+}
+
+// --------------------------------------------------------------------------
 // Warp-specialised grid kernel.  The T data threads own the rows and stream
 // X; one extra wave owns the grid reduction: it sums the data waves' partials,
 // publishes them, and polls the other workgroups' words.  Vector loads of a
@@ -1601,8 +2091,15 @@ struct Variant {
   X_(F32, 512, 2, 8, 2) X_(F32, 512, 2, 4, 1) X_(F32, 256, 4, 4, 1) X_(F32, 256, 4, 8, 2) X_(BF16, 512, 1, 8, 2)
 #define HPSCD_XENTRY(S, T, R, B, NPW) \
   {T, R, B, HPSCD_IS_BF16_##S, true, 5, reinterpret_cast<const void*>(&k_sweep_px<S, T, R, B, NPW>), T},
+#define HPSCD_PE_VARIANTS(X_)                                                                               \
+  X_(F32, 512, 2, 8, 2) X_(F32, 512, 2, 8, 3) X_(F32, 1024, 1, 8, 2) X_(F32, 512, 2, 4, 2) X_(F32, 512, 2, 4, 3) \
+  X_(BF16, 512, 1, 8, 2) X_(BF16, 512, 1, 8, 3)
+// kind 6: ring of 2 blocks; kind 7: ring of 3
+#define HPSCD_EENTRY(S, T, R, B, D) \
+  {T, R, B, HPSCD_IS_BF16_##S, true, 4 + D, reinterpret_cast<const void*>(&k_sweep_pe<S, T, R, B, D>), T},
 static const Variant kVariants[] = {HPSCD_SWEEP_VARIANTS(HPSCD_ENTRY) HPSCD_PIPE_VARIANTS(HPSCD_PENTRY)
-                                        HPSCD_WS_VARIANTS(HPSCD_WENTRY) HPSCD_PX_VARIANTS(HPSCD_XENTRY)};
+                                        HPSCD_WS_VARIANTS(HPSCD_WENTRY) HPSCD_PX_VARIANTS(HPSCD_XENTRY)
+                                            HPSCD_PE_VARIANTS(HPSCD_EENTRY)};
 
 // The deepest prefetch ring built for the shape (D = 0: any).
 static const Variant* find_variant(int T, int R, int B, bool bf16, bool grid, int D = 0) {
@@ -1620,7 +2117,7 @@ bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid, int D) {
 int sweep_max_workgroups(int T, int R, int B, bool bf16, bool grid, int D) {
   const Variant* v = find_variant(T, R, B, bf16, grid, D);
   if (!v) return 0;
-  return (v->D >= 10 || v->D == 5) ? 256 : 512;
+  return (v->D >= 10 || v->D == 5 || v->D == 6 || v->D == 7) ? 256 : 512;
 }
 
 int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid, int D) {

@@ -116,6 +116,10 @@ def test_tall_large_full_size_two_sweeps(lib):
     say("info", r.info)
     for kind in (12, 13):
         check(lib, s, 2, block=4, depth=kind)
+    for kind, tt in ((6, 512), (6, 1024), (7, 512)):
+        say("column blocks in flight", kind, tt)
+        r, _ = check(lib, s, 2, depth=kind, team_threads=tt)
+        assert r.info["kernel_kind"] == kind and r.info["team_threads"] == tt
 
 
 def test_wide_workgroup(lib):
@@ -220,12 +224,13 @@ def test_residual_f64(lib):
 
 # ------------------------------------------------------------ pipelined grid
 
-@pytest.mark.parametrize("block,kind", [(2, 4), (4, 4), (4, 12), (4, 13), (8, 12), (8, 5), (4, 5)])
+@pytest.mark.parametrize("block,kind", [(2, 4), (4, 4), (4, 12), (4, 13), (8, 12), (8, 5), (4, 5), (8, 6), (4, 6),
+                                        (8, 7), (4, 7)])
 def test_grid_kernel_kinds_match_oracle(lib, block, kind):
     """Every grid kernel kind (pipelined reductions with the cross-block Gram
     correction; warp-specialised with a two- or three-block ring; polling
-    waves fed through LDS) produces the iterates of Algorithm 1 (n not a
-    multiple of the block, ragged rows)."""
+    waves fed through LDS; two blocks in flight) produces the iterates of
+    Algorithm 1 (n not a multiple of the block, ragged rows)."""
     s = gen.tall_large(m=300_003, n=37, seed=13, pad=np.nan)
     say("grid kind", block, kind)
     r, ref = check(lib, s, 6, block=block, depth=kind)
@@ -265,3 +270,36 @@ def test_polling_wave_kernel_shapes(lib, team_threads):
     ref_eq = oracle.solve(s.Xt, s.y, s.m, a0=a0.astype(np.float64), max_sweeps=r.info["sweeps_done"])
     assert rel(r.a.cpu().numpy(), ref_eq.a) <= 1e-5
     assert r.info["team_threads"] == team_threads and r.info["team_wgs"] > 1
+
+
+@pytest.mark.parametrize("kind,team_threads,m,n,stop", [(6, 512, 200_001, 45, "change"), (6, 1024, 120_013, 45, "change"),
+                                                         (6, 512, 100_003, 48, "resid"), (7, 512, 200_001, 45, "change"),
+                                                         (7, 512, 100_003, 48, "resid"), (7, 512, 99_999, 47, "change")])
+def test_blocks_in_flight_kernel(lib, kind, team_threads, m, n, stop):
+    """The grid kernel with one polling wave and a ring of two (kind 6) or
+    three (kind 7) column blocks on ragged systems with a warm start,
+    stopping inside the loop:
+    on the relative change of ||e|| at a sweep end, or on the relative
+    residual at a column check inside a sweep.  The stop lands where the
+    oracle's does and the iterate matches the oracle's after as many steps."""
+    s = gen.tall_large(m=m, n=n, seed=29, pad=np.nan)
+    say("pe", kind, team_threads, m, stop)
+    rng = np.random.default_rng(4)
+    a0 = rng.standard_normal(s.n).astype(np.float32)
+    if stop == "change":
+        kw, okw = dict(stop=lib.STOP_REL_CHANGE, tol=1e-5), dict(stop=oracle.STOP_REL_CHANGE, tol=1e-5)
+    else:
+        kw = dict(stop=lib.STOP_REL_RESID, tol=0.015, check_cols=8)
+        okw = dict(stop=oracle.STOP_REL_RESID, tol=0.015, check_cols=8)
+    r = lib.solve(dev(s.Xt), dev(s.y), dev(a0), max_sweeps=30, block=8, depth=kind, team_threads=team_threads,
+                  flags=lib.F_FORCE_GRID, **kw)
+    ref = oracle.solve(s.Xt, s.y, s.m, a0=a0.astype(np.float64), max_sweeps=30, **okw)
+    assert r.info["kernel_kind"] == kind and r.info["team_wgs"] > 1
+    assert r.info["converged"] == 1
+    if stop == "change":
+        assert abs(r.info["sweeps_done"] - ref.sweeps) <= 1
+        ref_eq = oracle.solve(s.Xt, s.y, s.m, a0=a0.astype(np.float64), max_sweeps=r.info["sweeps_done"])
+        assert rel(r.a.cpu().numpy(), ref_eq.a) <= 1e-5
+    else:
+        assert r.info["cols_done"] == ref.cols and ref.cols % n != 0  # a check inside a sweep
+        assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
