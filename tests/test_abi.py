@@ -94,6 +94,19 @@ def test_validation_accepts(hp):
     assert hp.validate(100, 10, 4096, 104, 2, 64, o, 128) == hp.OK
 
 
+@pytest.mark.parametrize("depth", [0, 2, 3, 4, 5, 6, 7, 12, 13])
+def test_kernel_kinds_accepted(hp, depth):
+    o = hp.make_opts(5, depth=depth)
+    assert hp.validate(100, 10, 4096, 100, 4, 64, o, 128) == hp.OK
+
+
+@pytest.mark.parametrize("depth", [1, 8, 11, 14, -1])
+def test_unknown_kernel_kind_rejected(hp, depth):
+    o = hp.make_opts(5, depth=depth)
+    assert hp.validate(100, 10, 4096, 100, 4, 64, o, 128) == hp.EINVAL
+    assert "depth" in hp.last_error()
+
+
 def test_null_context_rejected(hp):
     o = hp.make_opts(5)
     st = hp._lib.hpscd_solve_f32(None, 100, 10, 4096, 100, 64, None, ctypes.byref(o), 128, None, None, None)
