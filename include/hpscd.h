@@ -68,7 +68,7 @@ typedef struct {
   double tol;           /* finite, >= 0; ignored by HPSCD_STOP_NONE */
   int64_t check_cols;   /* >= 0, see HPSCD_STOP_REL_RESID (rounded to the block size) */
   int64_t refresh_cols; /* bf16 form: e = y - X32·a (FP64 sums) every refresh_cols column steps; 0 = never */
-  int32_t block;        /* columns per reduction round (1, 2, 4 or 8); 0 = library choice */
+  int32_t block;        /* columns per reduction round (1, 2, 4, 8, or 16 with depth 8); 0 = library choice */
   int32_t flags;        /* HPSCD_F_* */
   int32_t team_threads; /* threads per workgroup; 0 = library choice */
   int32_t depth;        /* kernel kind; 0 = library choice.  2, 3: prefetch ring of 2 or 3 blocks;
@@ -76,8 +76,9 @@ typedef struct {
                            5: grid kernel whose polling waves never wait behind column loads
                            (their rows arrive through LDS); 6, 7: grid kernel with one polling
                            wave and a ring of 2 or 3 column blocks requested as soon as a
-                           buffer frees; 12, 13: grid kernel with a dedicated reduction wave,
-                           ring of 2 or 3 */
+                           buffer frees; 8: grid kernel with 16-column blocks and no column
+                           loads in flight during the exchange; 12, 13: grid kernel with a
+                           dedicated reduction wave, ring of 2 or 3 */
 } hpscd_opts;
 
 typedef struct {

@@ -122,6 +122,26 @@ __global__ void __launch_bounds__(256) k_colgram_reduce(const double* partial, i
   }
 }
 
+// Tables of 16-column blocks from those of 8-column blocks: the strictly
+// lower in-block Gram of block b holds the in-block Gram entries of its two
+// halves and the Gram of the second half against the first.  One thread per
+// entry (l, i), i < l, at l(l-1)/2 + i.
+__global__ void __launch_bounds__(256) k_gram16(const double* gram8, const double* cross8, int64_t nb8,
+                                                int64_t nb16, double* gram16) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= nb16 * 120) return;
+  const int64_t b = t / 120;
+  const int q = (int)(t % 120);
+  int l = 1;
+  while (l * (l - 1) / 2 + l <= q) ++l;
+  const int i = q - l * (l - 1) / 2;
+  const int64_t h0 = 2 * b, h1 = 2 * b + 1;
+  double v = 0.0;
+  if (l < 8) v = gram8[h0 * 28 + l * (l - 1) / 2 + i];
+  else if (h1 < nb8) v = (i >= 8) ? gram8[h1 * 28 + (l - 8) * (l - 9) / 2 + (i - 8)] : cross8[h1 * 64 + (l - 8) * 8 + i];
+  gram16[b * 120 + q] = v;
+}
+
 template <class S, int B, bool CROSS>
 static hipError_t colgram_impl(const void* X, int64_t ldx, int64_t m, int64_t n, double* rdn, double* gram,
                                double* cross, double* partial, int64_t partial_cap, int32_t* ctl,
@@ -166,6 +186,25 @@ hipError_t launch_colgram(const void* X, bool bf16, int64_t ldx, int64_t m, int6
                                                zero_cols, s);
   switch (B) {
     HPSCD_CG(1) HPSCD_CG(2) HPSCD_CG(4) HPSCD_CG(8)
+    case 16: {
+      // 16-column tables from one pass of the 8-column statistics with the
+      // Gram of each block against the previous one (cross must hold
+      // nb16 * 256 doubles: the 8-column cross Gram, then the 8-column
+      // in-block Gram)
+      if (cross == nullptr) return hipErrorInvalidValue;
+      const int64_t nb8 = (n + 7) / 8, nb16 = (n + 15) / 16;
+      double* cross8 = cross;
+      double* gram8 = cross + nb8 * 64;
+      hipError_t err = launch_fill_f64(rdn + nb8 * 8, nb16 * 16 - nb8 * 8, 0.0, s);
+      if (err != hipSuccess) return err;
+      err = bf16 ? colgram_impl<BF16, 8, true>(X, ldx, m, n, rdn, gram8, cross8, partial, partial_cap, ctl, zero_cols, s)
+                 : colgram_impl<F32, 8, true>(X, ldx, m, n, rdn, gram8, cross8, partial, partial_cap, ctl, zero_cols, s);
+      if (err != hipSuccess) return err;
+      const int64_t total = nb16 * 120;
+      hipLaunchKernelGGL(k_gram16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, gram8, cross8, nb8, nb16,
+                         gram);
+      return hipGetLastError();
+    }
     default: return hipErrorInvalidValue;
   }
 #undef HPSCD_CG

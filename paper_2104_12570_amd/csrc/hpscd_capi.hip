@@ -131,11 +131,13 @@ hpscd_status validate_opts(const hpscd_opts* o) {
   if (!std::isfinite(o->tol) || o->tol < 0.0) return fail(HPSCD_EINVAL, "tol must be finite and >= 0");
   if (o->check_cols < 0) return fail(HPSCD_EINVAL, "check_cols must be >= 0");
   if (o->refresh_cols < 0) return fail(HPSCD_EINVAL, "refresh_cols must be >= 0");
-  if (o->block != 0 && o->block != 1 && o->block != 2 && o->block != 4 && o->block != 8)
-    return fail(HPSCD_EINVAL, "block must be 0, 1, 2, 4 or 8 (got %d)", o->block);
+  if (o->block != 0 && o->block != 1 && o->block != 2 && o->block != 4 && o->block != 8 && o->block != 16)
+    return fail(HPSCD_EINVAL, "block must be 0, 1, 2, 4, 8 or 16 (got %d)", o->block);
   if (o->depth != 0 && o->depth != 2 && o->depth != 3 && o->depth != 4 && o->depth != 5 && o->depth != 6 &&
-      o->depth != 7 && o->depth != 12 && o->depth != 13)
-    return fail(HPSCD_EINVAL, "depth (kernel kind) must be 0, 2, 3, 4, 5, 6, 7, 12 or 13 (got %d)", o->depth);
+      o->depth != 7 && o->depth != 8 && o->depth != 12 && o->depth != 13)
+    return fail(HPSCD_EINVAL, "depth (kernel kind) must be 0, 2, 3, 4, 5, 6, 7, 8, 12 or 13 (got %d)", o->depth);
+  if (o->block == 16 && o->depth != 0 && o->depth != 8)
+    return fail(HPSCD_EINVAL, "block 16 runs only on the wide-block grid kernel (depth 8)");
   if ((o->flags & HPSCD_F_FORCE_GRID) && (o->flags & HPSCD_F_FORCE_WG))
     return fail(HPSCD_EINVAL, "FORCE_GRID and FORCE_WG are exclusive");
   if ((int64_t)o->max_sweeps + 1 > (int64_t)1 << 30) return fail(HPSCD_EINVAL, "max_sweeps too large");
@@ -175,7 +177,13 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
     if (bf16) shapes = {{256, 1}, {256, 2}};
     else shapes = {{256, 2}, {256, 4}};
   }
-  const int want = o->block > 0 ? o->block : (grid ? 8 : 4);
+  // the wide-block kernel: 16 columns per reduction
+  const bool wide = grid && (o->depth == 8 || (o->depth == 0 && o->block == 16));
+  if (wide) {
+    if (bf16) shapes = {{512, 1}};
+    else shapes = {{512, 2}};
+  }
+  const int want = o->block > 0 ? o->block : (wide ? 16 : (grid ? 8 : 4));
   // Stop checks and refreshes fall at block starts, counted in column steps
   // from the start of the solve: the block must divide n for those to land
   // on every multiple of check_cols (refresh_cols).
@@ -196,6 +204,7 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
   if (grid && o->depth == 4 && o->check_cols > 0 && o->stop == HPSCD_STOP_REL_RESID)
     return fail(HPSCD_EINVAL, "the pipelined kernel (depth 4) tests the stop rule only at sweep ends");
   if (o->depth != 0) kinds = {o->depth};
+  else if (wide) kinds = {8};
   else if (grid) kinds = {5, 2, 3};  // measured fastest on the 1M x 256 system; 4, 12, 13 are selectable
   else kinds = {4, 3, 2};         // one workgroup: the deepest ring hides the most load latency
   auto kind_of = [&](int T, int R, int b) {
@@ -233,6 +242,7 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
 uint32_t poll_delay_ticks(const Plan& pl) {
   if (!pl.grid) return 0;
   if (pl.D == 5 || pl.D == 6 || pl.D == 7) return (uint32_t)std::min(240.0, 80.0 + 0.6 * pl.P);
+  if (pl.D == 8) return (uint32_t)std::min(100.0, 0.2 * pl.P);  // no column loads in flight during the exchange
   if (pl.D == 2 || pl.D == 3) return (uint32_t)std::min(160.0, 0.65 * pl.P);
   return 0;
 }
@@ -303,7 +313,7 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   }
   const bool pipelined = pl.grid && pl.D == 4;  // (one workgroup: D = 4 is a 4-block ring)
   HIP_TRY(launch_colgram(Xs, bf16, ldxs, m, n, B, c->rdn.as<double>(), c->gram.as<double>(),
-                         pipelined ? c->cross.as<double>() : nullptr, partial, partial_cap,
+                         (pipelined || B == 16) ? c->cross.as<double>() : nullptr, partial, partial_cap,
                          ctl, &ctl64[C64_ZERO_COLS], st));
   HIP_TRY(hipEventRecord(c->ev[1], st));
 

@@ -1230,6 +1230,273 @@ __global__ void __launch_bounds__(T) k_sweep_pe(SolveArgs A) {
 }
 
 // --------------------------------------------------------------------------
+// Grid kernel with wide blocks and no prefetch.
+//
+// One grid-wide reduction per block of B = 16 columns instead of 8: every
+// wave loads its rows of the block, computes the partial sums, and the
+// workgroup then exchanges them with the grid while no column load is in
+// flight, so the exchange's loads and stores never queue behind column data.
+// The block is requested again only after its axpy.  On the 1M x 256 system
+// the column stream of a 16-column block (256 KB per CU) plus one exchange
+// takes less than two exchanges of 8-column blocks, each overlapped with the
+// next block's loads in the same CU memory pipeline.
+// The exchange is spread over the waves: value v of the block is polled and
+// summed by wave v mod NW.  Arithmetic and stop logic are those of k_sweep;
+// only the order of the fixed-order sums differs.
+template <class S, int T, int R, int B>
+__global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
+  using raw = typename S::raw_t;
+  constexpr int VEC = S::VEC;
+  constexpr int NW = T / WAVE;
+  constexpr int NV = B + 1;
+  constexpr int MAXC = 4;                      // up to 256 workgroups
+  constexpr int VPW = (NV + NW - 1) / NW;      // values summed by one wave, at most
+  constexpr long long TIMED_OUT = 0x7ff8000000000001ll;  // a NaN no arithmetic here produces
+  __shared__ float red[NW][NV];
+  __shared__ double stot[NV];
+
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
+  const int wg = (int)blockIdx.x;
+  const int64_t m = A.m, n = A.n;
+  const int nb = (int)((n + B - 1) / B);
+  if (A.ctl[CTL_NONFINITE] != 0 || A.ctl[CTL_DONE] != 0) return;
+
+  float e[R][VEC];
+  int lim[R];
+  uint32_t boff[R];
+  const int64_t wg_row0 = (int64_t)wg * (T * R * VEC);
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    const int64_t r0 = wg_row0 + (int64_t)VEC * (tid + T * c);
+    const int64_t left = m - r0;
+    lim[c] = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
+    // a chunk with no valid row reads the workgroup's first chunk (finite
+    // data; its residual is held at zero)
+    boff[c] = (uint32_t)((lim[c] > 0 ? r0 : wg_row0) * (16 / VEC));
+#pragma unroll
+    for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? A.e0[r0 + i] : 0.f;
+  }
+  const bool ragged = wg_row0 + (T * R * VEC) > m;
+  bool straddle[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) straddle[c] = __ballot(lim[c] > 0 && lim[c] < VEC) != 0;
+
+  double prev_norm = A.fstat[1];
+  const double ynorm = sqrt(*A.ynorm2);
+  const int64_t nblocks = A.blk_end - A.blk_begin;
+  const int64_t col_bytes = A.ldx * (int64_t)(16 / VEC);
+  int bi = (int)(A.blk_begin % nb);
+  int sdone = (int)(A.blk_begin / nb);
+  uint32_t seq = (uint32_t)(A.blk_begin + 1);
+
+  auto finalize = [&](int sd, bool conv, int64_t cols, double nrm2) {
+    if (wg == 0 && tid == 0) {
+      A.ctl[CTL_SWEEPS] = sd;
+      A.ctl[CTL_CONVERGED] = conv ? 1 : 0;
+      A.ctl[CTL_DONE] = 1;
+      A.ctl64[C64_COLS] = cols;
+      A.fstat[0] = nrm2;
+    }
+  };
+
+  for (int64_t k = 0; k < nblocks; ++k) {
+    const int j0 = bi * B;
+    // the block's columns (loads past the last column return zero)
+    raw x[B][R];
+    {
+      const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
+      const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
+      const uint32_t nrec = span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<char*>(reinterpret_cast<const char*>(A.X) + (int64_t)j0 * col_bytes), 0, (int)nrec, 0x00020000);
+#pragma unroll
+      for (int l = 0; l < B; ++l)
+#pragma unroll
+        for (int c = 0; c < R; ++c)
+          x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
+    }
+    Coef<B> cf;
+    cf.load(A.rdn, A.gram, bi, lane);
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+      if (straddle[c]) {  // wave-uniform
+#pragma unroll
+        for (int l = 0; l < B; ++l)
+          if (lim[c] > 0 && lim[c] < VEC) x[l][c] = mask_chunk<S>(x[l][c], lim[c]);
+      }
+    // partial sums of this wave's rows
+    float p[NV];
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(x[l][c], i), e[c][i], acc);
+      p[l] = acc;
+    }
+    {
+      float acc = 0.f;
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) acc = fmaf(e[c][i], e[c][i], acc);
+      p[B] = acc;
+    }
+#pragma unroll
+    for (int l = 0; l < NV; ++l) {
+      const float v = wave_sum(p[l]);
+      if (lane == 0) red[wave][l] = v;
+    }
+    lds_barrier();
+    // exchange with the grid: wave 0 publishes the workgroup's sums; value v
+    // is polled and summed by wave v mod NW
+    const uint64_t* slot_base = A.slots + (int64_t)(seq & 1u) * NV * A.P;
+    bool injected = false;
+    if (wave == 0 && lane < NV) {
+      float sacc = 0.f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) sacc += red[w][lane];
+      // a cancel request rides the norm of a sweep's first block as a NaN
+      if (lane == B && bi == 0 && wg == 0 && load_flag(&A.ctl[CTL_ABORT]) != 0) {
+        sacc = __int_as_float(0x7fc00000);
+        injected = true;
+      }
+      publish(const_cast<uint64_t*>(slot_base) + (int64_t)lane * A.P + wg, seq, sacc);
+    }
+    const bool aborting = __ballot(injected) != 0;  // (meaningful in wave 0 of workgroup 0)
+    if (A.poll_delay) {
+      const uint64_t t0d = now_ticks();
+      while (now_ticks() - t0d < A.poll_delay) __builtin_amdgcn_s_sleep(2);
+    }
+    const int ncn = (A.P + WAVE - 1) / WAVE;
+    uint64_t w[VPW][MAXC];
+#pragma unroll
+    for (int q = 0; q < VPW; ++q) {
+      const int v = wave + NW * q;
+      const int vv = v < NV ? v : NV - 1;  // (rounds past the last value reread a valid word)
+#pragma unroll
+      for (int c = 0; c < MAXC; ++c) {
+        const int idx = c * WAVE + lane;
+        const bool live = c < ncn && idx < A.P;
+        w[q][c] = live ? peek(slot_base + (int64_t)vv * A.P + idx) : ((uint64_t)seq << 32);
+      }
+    }
+    uint64_t tstart = 0;
+    bool timed_out = false;
+    for (int spin = 0;; ++spin) {
+      bool ready = true;
+#pragma unroll
+      for (int q = 0; q < VPW; ++q)
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) ready = ready && ((uint32_t)(w[q][c] >> 32) == seq);
+      if (ready) break;
+      if (spin == 0) tstart = now_ticks();
+      else if (now_ticks() - tstart > A.timeout_ticks) {
+        timed_out = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+      for (int q = 0; q < VPW; ++q) {
+        const int v = wave + NW * q;
+        const int vv = v < NV ? v : NV - 1;
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+          const int idx = c * WAVE + lane;
+          if ((uint32_t)(w[q][c] >> 32) != seq) w[q][c] = peek(slot_base + (int64_t)vv * A.P + idx);
+        }
+      }
+    }
+    const bool any_timeout = __ballot(timed_out) != 0;
+    // fixed order: per lane over its chunks, then across the lanes
+#pragma unroll
+    for (int q = 0; q < VPW; ++q) {
+      const int v = wave + NW * q;
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < MAXC; ++c) {
+        const int idx = c * WAVE + lane;
+        acc += (c < ncn && idx < A.P) ? (double)__uint_as_float((uint32_t)w[q][c]) : 0.0;
+      }
+      const double tv = wave_sum(acc);
+      if (v < NV && lane == 0) stot[v] = any_timeout ? __longlong_as_double(TIMED_OUT) : tv;
+    }
+    lds_barrier();
+    double tot[NV];
+    bool tmo = false;  // some wave's poll timed out
+#pragma unroll
+    for (int l = 0; l < NV; ++l) {
+      tot[l] = uniform_f64(stot[l]);
+      tmo = tmo || (__double_as_longlong(tot[l]) == TIMED_OUT);
+    }
+    if (tmo) {
+      if (tid == 0) store_flag(&A.ctl[CTL_ERR], ERR_TIMEOUT);
+      break;
+    }
+    const double nrm2 = tot[B];
+    const double nrm = sqrt(nrm2);
+    if (!(nrm2 <= DBL_MAX)) {
+      if (wg == 0 && tid == 0) store_flag(&A.ctl[CTL_ERR], aborting ? ERR_ABORTED : ERR_NONFINITE);
+      finalize(sdone, false, (int64_t)sdone * n + j0, nrm2);
+      break;
+    }
+    if (bi == 0) {
+      if (wg == 0 && tid == 0) { A.hist[sdone] = nrm; A.fstat[1] = nrm; }
+      bool stop = false, conv = false;
+      if (A.stop != STOP_NONE && nrm2 == 0.0) stop = conv = true;
+      else if (A.stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < A.tol * nrm) stop = conv = true;
+      else if (A.stop == STOP_REL_RESID && nrm < A.tol * ynorm) stop = conv = true;
+      if (!stop && sdone >= A.max_sweeps) stop = true;
+      prev_norm = nrm;
+      if (stop) { finalize(sdone, conv, (int64_t)sdone * n, nrm2); break; }
+    } else if (A.check_cols > 0 && A.stop == STOP_REL_RESID) {
+      const int64_t cols = (int64_t)sdone * n + j0;
+      if (cols % A.check_cols == 0 && (nrm2 == 0.0 || nrm < A.tol * ynorm)) {
+        finalize(sdone, true, cols, nrm2);
+        break;
+      }
+    }
+    double da[B];
+    forward_substitute<B>(tot, cf, da);
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      const float f = (float)da[l];
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) e[c][i] = fmaf(-f, S::get(x[l][c], i), e[c][i]);
+    }
+    if (ragged) {
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? e[c][i] : 0.f;
+    }
+    if (tid < B) {
+      const int64_t j = j0 + tid;
+      if (j < n && (int)(j % A.P) == wg) {
+        double d = 0.0;
+#pragma unroll
+        for (int l = 0; l < B; ++l) if (tid == l) d = da[l];
+        (void)__hip_atomic_fetch_add(&A.a64[j], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    bi = (bi + 1 == nb) ? 0 : bi + 1;
+    if (bi == 0) ++sdone;
+    ++seq;
+  }
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    const int64_t r0 = wg_row0 + (int64_t)VEC * (tid + T * c);
+#pragma unroll
+    for (int i = 0; i < VEC; ++i)
+      if (i < lim[c]) A.e_out[r0 + i] = e[c][i];
+  }
+}
+
+// --------------------------------------------------------------------------
 // Warp-specialised grid kernel.  The T data threads own the rows and stream
 // X; one extra wave owns the grid reduction: it sums the data waves' partials,
 // publishes them, and polls the other workgroups' words.  Vector loads of a
@@ -2097,9 +2364,13 @@ struct Variant {
 // kind 6: ring of 2 blocks; kind 7: ring of 3
 #define HPSCD_EENTRY(S, T, R, B, D) \
   {T, R, B, HPSCD_IS_BF16_##S, true, 4 + D, reinterpret_cast<const void*>(&k_sweep_pe<S, T, R, B, D>), T},
+// kind 8: wide blocks, no prefetch
+#define HPSCD_WIDE_VARIANTS(X_) X_(F32, 512, 2, 16) X_(BF16, 512, 1, 16)
+#define HPSCD_WBENTRY(S, T, R, B) \
+  {T, R, B, HPSCD_IS_BF16_##S, true, 8, reinterpret_cast<const void*>(&k_sweep_wide<S, T, R, B>), T},
 static const Variant kVariants[] = {HPSCD_SWEEP_VARIANTS(HPSCD_ENTRY) HPSCD_PIPE_VARIANTS(HPSCD_PENTRY)
                                         HPSCD_WS_VARIANTS(HPSCD_WENTRY) HPSCD_PX_VARIANTS(HPSCD_XENTRY)
-                                            HPSCD_PE_VARIANTS(HPSCD_EENTRY)};
+                                            HPSCD_PE_VARIANTS(HPSCD_EENTRY) HPSCD_WIDE_VARIANTS(HPSCD_WBENTRY)};
 
 // The deepest prefetch ring built for the shape (D = 0: any).
 static const Variant* find_variant(int T, int R, int B, bool bf16, bool grid, int D = 0) {
@@ -2117,7 +2388,7 @@ bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid, int D) {
 int sweep_max_workgroups(int T, int R, int B, bool bf16, bool grid, int D) {
   const Variant* v = find_variant(T, R, B, bf16, grid, D);
   if (!v) return 0;
-  return (v->D >= 10 || v->D == 5 || v->D == 6 || v->D == 7) ? 256 : 512;
+  return (v->D >= 10 || (v->D >= 5 && v->D <= 8)) ? 256 : 512;
 }
 
 int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid, int D) {

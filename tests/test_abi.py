@@ -77,6 +77,7 @@ def test_version(hp):
     (dict(tol=float("nan")), "tol"),
     (dict(tol=-1.0), "tol"),
     (dict(block=3), "block"),
+    (dict(block=32), "block"),
     (dict(flags=2 | 4), "exclusive"),
 ])
 def test_validation_rejects(hp, case, msg):
@@ -94,13 +95,13 @@ def test_validation_accepts(hp):
     assert hp.validate(100, 10, 4096, 104, 2, 64, o, 128) == hp.OK
 
 
-@pytest.mark.parametrize("depth", [0, 2, 3, 4, 5, 6, 7, 12, 13])
+@pytest.mark.parametrize("depth", [0, 2, 3, 4, 5, 6, 7, 8, 12, 13])
 def test_kernel_kinds_accepted(hp, depth):
     o = hp.make_opts(5, depth=depth)
     assert hp.validate(100, 10, 4096, 100, 4, 64, o, 128) == hp.OK
 
 
-@pytest.mark.parametrize("depth", [1, 8, 11, 14, -1])
+@pytest.mark.parametrize("depth", [1, 9, 11, 14, -1])
 def test_unknown_kernel_kind_rejected(hp, depth):
     o = hp.make_opts(5, depth=depth)
     assert hp.validate(100, 10, 4096, 100, 4, 64, o, 128) == hp.EINVAL
@@ -170,3 +171,10 @@ def test_batched_plan_rejects_bad_arguments(hp):
     assert hp._lib.hpscd_batched_plan_launch(None, None) == hp.EINVAL
     assert hp._lib.hpscd_batched_plan_results(None, None, None, None, None, None, None) == hp.EINVAL
     hp._lib.hpscd_batched_plan_destroy(None)
+
+
+def test_wide_block_needs_the_wide_kernel(hp):
+    assert hp.validate(100, 10, 4096, 100, 4, 64, hp.make_opts(5, block=16, depth=8), 128) == hp.OK
+    assert hp.validate(100, 10, 4096, 100, 4, 64, hp.make_opts(5, block=16), 128) == hp.OK
+    assert hp.validate(100, 10, 4096, 100, 4, 64, hp.make_opts(5, block=16, depth=5), 128) == hp.EINVAL
+    assert "depth 8" in hp.last_error()

@@ -258,18 +258,18 @@ def test_bf16_polling_wave_kernel(lib):
     assert np.all(np.abs(np.asarray(r.hist) - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0])
 
 
-@pytest.mark.parametrize("kind", [6, 7])
+@pytest.mark.parametrize("kind", [6, 7, 8])
 def test_bf16_blocks_in_flight_kernel(lib, kind):
     """The storage form through the grid kernel with a ring of two (kind 6)
     or three (kind 7) column blocks, with refreshes between launch segments,
     against the oracle of the form."""
-    s = gen.tall_large(m=150_000, n=40, seed=23)
+    s = gen.tall_large(m=150_000, n=48 if kind == 8 else 40, seed=23)
     X32 = dev(s.Xt)
     Xb = lib.convert_bf16(X32)
     say("bf16 pe", kind)
-    r = lib.solve_bf16(Xb, X32, dev(s.y), max_sweeps=4, refresh_cols=40, block=8, depth=kind, team_threads=512,
-                       flags=lib.F_FORCE_GRID)
-    ref = oracle.solve_bf16_refresh(s.Xt, s.y, s.m, max_sweeps=4, refresh_cols=40)
+    r = lib.solve_bf16(Xb, X32, dev(s.y), max_sweeps=4, refresh_cols=80 if kind == 8 else 40,
+                       block=16 if kind == 8 else 8, depth=kind, team_threads=512, flags=lib.F_FORCE_GRID)
+    ref = oracle.solve_bf16_refresh(s.Xt, s.y, s.m, max_sweeps=4, refresh_cols=80 if kind == 8 else 40)
     assert r.info["kernel_kind"] == kind
     assert r.info["refreshes"] == ref.refreshes
     assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5

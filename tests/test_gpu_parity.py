@@ -116,7 +116,7 @@ def test_tall_large_full_size_two_sweeps(lib):
     say("info", r.info)
     for kind in (12, 13):
         check(lib, s, 2, block=4, depth=kind)
-    for kind, tt in ((6, 512), (6, 1024), (7, 512)):
+    for kind, tt in ((6, 512), (6, 1024), (7, 512), (8, 512)):
         say("column blocks in flight", kind, tt)
         r, _ = check(lib, s, 2, depth=kind, team_threads=tt)
         assert r.info["kernel_kind"] == kind and r.info["team_threads"] == tt
@@ -225,7 +225,7 @@ def test_residual_f64(lib):
 # ------------------------------------------------------------ pipelined grid
 
 @pytest.mark.parametrize("block,kind", [(2, 4), (4, 4), (4, 12), (4, 13), (8, 12), (8, 5), (4, 5), (8, 6), (4, 6),
-                                        (8, 7), (4, 7)])
+                                        (8, 7), (4, 7), (16, 8)])
 def test_grid_kernel_kinds_match_oracle(lib, block, kind):
     """Every grid kernel kind (pipelined reductions with the cross-block Gram
     correction; warp-specialised with a two- or three-block ring; polling
@@ -274,11 +274,13 @@ def test_polling_wave_kernel_shapes(lib, team_threads):
 
 @pytest.mark.parametrize("kind,team_threads,m,n,stop", [(6, 512, 200_001, 45, "change"), (6, 1024, 120_013, 45, "change"),
                                                          (6, 512, 100_003, 48, "resid"), (7, 512, 200_001, 45, "change"),
-                                                         (7, 512, 100_003, 48, "resid"), (7, 512, 99_999, 47, "change")])
+                                                         (7, 512, 100_003, 48, "resid"), (7, 512, 99_999, 47, "change"),
+                                                         (8, 512, 200_001, 45, "change"), (8, 512, 100_003, 48, "resid")])
 def test_blocks_in_flight_kernel(lib, kind, team_threads, m, n, stop):
     """The grid kernel with one polling wave and a ring of two (kind 6) or
-    three (kind 7) column blocks on ragged systems with a warm start,
-    stopping inside the loop:
+    three (kind 7) column blocks, and the wide-block kernel (kind 8, 16
+    columns per reduction), on ragged systems with a warm start, stopping
+    inside the loop:
     on the relative change of ||e|| at a sweep end, or on the relative
     residual at a column check inside a sweep.  The stop lands where the
     oracle's does and the iterate matches the oracle's after as many steps."""
@@ -289,10 +291,11 @@ def test_blocks_in_flight_kernel(lib, kind, team_threads, m, n, stop):
     if stop == "change":
         kw, okw = dict(stop=lib.STOP_REL_CHANGE, tol=1e-5), dict(stop=oracle.STOP_REL_CHANGE, tol=1e-5)
     else:
-        kw = dict(stop=lib.STOP_REL_RESID, tol=0.015, check_cols=8)
-        okw = dict(stop=oracle.STOP_REL_RESID, tol=0.015, check_cols=8)
-    r = lib.solve(dev(s.Xt), dev(s.y), dev(a0), max_sweeps=30, block=8, depth=kind, team_threads=team_threads,
-                  flags=lib.F_FORCE_GRID, **kw)
+        cc = 16 if kind == 8 else 8  # (the block divides check_cols)
+        kw = dict(stop=lib.STOP_REL_RESID, tol=0.015, check_cols=cc)
+        okw = dict(stop=oracle.STOP_REL_RESID, tol=0.015, check_cols=cc)
+    r = lib.solve(dev(s.Xt), dev(s.y), dev(a0), max_sweeps=30, block=16 if kind == 8 else 8, depth=kind,
+                  team_threads=team_threads, flags=lib.F_FORCE_GRID, **kw)
     ref = oracle.solve(s.Xt, s.y, s.m, a0=a0.astype(np.float64), max_sweeps=30, **okw)
     assert r.info["kernel_kind"] == kind and r.info["team_wgs"] > 1
     assert r.info["converged"] == 1
