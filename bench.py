@@ -367,7 +367,11 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic("k_sweep_f32_tall_1000000x256", sweeps)
             if (s.m, s.n, args.fixed_sweeps) == (1_000_000, 256, 0) else None,
-            "kernel": {5: "k_sweep_px (persistent grid, polling waves fed through LDS)",
+            "kernel": {8: "k_sweep_wide (persistent grid, 16-column blocks, no column loads in flight "
+                          "during the exchange)",
+                       5: "k_sweep_px (persistent grid, polling waves fed through LDS)",
+                       6: "k_sweep_pe (persistent grid, one polling wave, 2-block ring)",
+                       7: "k_sweep_pe (persistent grid, one polling wave, 3-block ring)",
                        2: "k_sweep (persistent grid, 2-block ring)",
                        3: "k_sweep (persistent grid, 3-block ring)"}.get(info["kernel_kind"],
                                                                          f"sweep kernel kind {info['kernel_kind']}"),

@@ -84,6 +84,50 @@ __global__ void __launch_bounds__(256) k_colgram(const void* X, int64_t ldx, int
   }
 }
 
+// The same statistics for blocks of 16 columns on the matrix cores: the
+// block's Gram matrix X_b^T X_b is a dense contraction over the rows, summed
+// with v_mfma_f64_16x16x4 (FP64 products of the FP32 or BF16 values, exact,
+// and FP64 sums).  Lane (j, k) = (lane % 16, lane / 16) loads 16 bytes of
+// column j at rows row + k*VEC ..; multiply-add t takes element t of every
+// lane, i.e. rows {row + k*VEC + t : k < 4} as its K = 4 slice, and the
+// same register is both operands (A = X^T, B = X).  The accumulator holds
+// G[lane/16 + 4*v][lane % 16] in element v (the instruction's result layout,
+// checked on the device); the entries (l, i <= l) go to the partial sums in
+// the layout of k_colgram.
+template <class S>
+__global__ void __launch_bounds__(256) k_colgram16_mfma(const void* X, int64_t ldx, int64_t m, int64_t n,
+                                                        int64_t rows_per, double* partial) {
+  using raw = typename S::raw_t;
+  constexpr int VEC = S::VEC, B = 16, NP = B * (B + 1) / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, kq = lane >> 4;
+  const int64_t nb = (n + B - 1) / B;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t r1 = min(m, r0 + rows_per);
+  for (int64_t b = (int64_t)blockIdx.y * 4 + wave; b < nb; b += (int64_t)gridDim.y * 4) {
+    const int64_t col = b * B + j;
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t row = r0; row < r1; row += 4 * VEC) {
+      const int64_t rr = row + (int64_t)kq * VEC;
+      const int64_t left = r1 - rr;
+      const int lim = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
+      raw x = (col < n && lim > 0) ? load_chunk<S>(X, col * ldx + rr) : S::zero();
+      if (lim < VEC) x = mask_chunk<S>(x, lim);
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) {
+        const double v = (double)chunk_at<S>(x, t);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int l = kq + 4 * v, i = j;
+      if (i <= l) partial[((int64_t)blockIdx.x * nb + b) * NP + l * (l + 1) / 2 + i] = acc[v];
+    }
+  }
+}
+
 // Sum the PR partials (fixed order, one wave per output) into rdn[nb*B],
 // gram[nb*NG] and (CROSS) cross[nb*B*B].
 template <int B, bool CROSS>
@@ -170,6 +214,34 @@ static hipError_t colgram_impl(const void* X, int64_t ldx, int64_t m, int64_t n,
   return hipGetLastError();
 }
 
+// As colgram_impl for blocks of 16 columns, the partial sums on the matrix
+// cores (k_colgram16_mfma); the same reduction.
+template <class S>
+static hipError_t colgram16_mfma(const void* X, int64_t ldx, int64_t m, int64_t n, double* rdn, double* gram,
+                                 double* partial, int64_t partial_cap, int32_t* ctl, int64_t* zero_cols,
+                                 hipStream_t s) {
+  constexpr int B = 16, NPX = B * (B + 1) / 2;
+  const int64_t nb = (n + B - 1) / B;
+  int64_t PR = 1;
+  if (nb < 8192) PR = (8192 + nb - 1) / nb;
+  const int64_t min_rows = 4 * S::VEC * 16;
+  PR = std::max<int64_t>(1, std::min<int64_t>(PR, (m + min_rows - 1) / min_rows));
+  while (PR > 1 && PR * nb * NPX > partial_cap) --PR;
+  if (PR * nb * NPX > partial_cap) return hipErrorInvalidValue;
+  int64_t rows_per = (m + PR - 1) / PR;
+  rows_per = (rows_per + 4 * S::VEC - 1) / (4 * S::VEC) * (4 * S::VEC);
+  PR = (m + rows_per - 1) / rows_per;
+  const int64_t NBG = std::min<int64_t>((nb + 3) / 4, 65535);
+  hipLaunchKernelGGL((k_colgram16_mfma<S>), dim3((unsigned)PR, (unsigned)NBG), dim3(256), 0, s, X, ldx, m, n,
+                     rows_per, partial);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const int64_t total = nb * NPX;
+  hipLaunchKernelGGL((k_colgram_reduce<B, false>), dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, partial,
+                     (int)PR, n, rdn, gram, nullptr, ctl, zero_cols);
+  return hipGetLastError();
+}
+
 hipError_t launch_colgram(const void* X, bool bf16, int64_t ldx, int64_t m, int64_t n, int B, double* rdn,
                           double* gram, double* cross, double* partial, int64_t partial_cap, int32_t* ctl,
                           int64_t* zero_cols, hipStream_t s) {
@@ -187,18 +259,18 @@ hipError_t launch_colgram(const void* X, bool bf16, int64_t ldx, int64_t m, int6
   switch (B) {
     HPSCD_CG(1) HPSCD_CG(2) HPSCD_CG(4) HPSCD_CG(8)
     case 16: {
-      // 16-column tables from one pass of the 8-column statistics with the
-      // Gram of each block against the previous one (cross must hold
-      // nb16 * 256 doubles: the 8-column cross Gram, then the 8-column
-      // in-block Gram)
+      // FP32: one pass of the 16-column statistics.  BF16: the 16-column
+      // tables from one pass of the 8-column statistics with the Gram of each
+      // block against the previous one (cross must hold nb16 * 256 doubles:
+      // the 8-column cross Gram, then the 8-column in-block Gram).
+      if (!bf16) return colgram16_mfma<F32>(X, ldx, m, n, rdn, gram, partial, partial_cap, ctl, zero_cols, s);
       if (cross == nullptr) return hipErrorInvalidValue;
       const int64_t nb8 = (n + 7) / 8, nb16 = (n + 15) / 16;
       double* cross8 = cross;
       double* gram8 = cross + nb8 * 64;
       hipError_t err = launch_fill_f64(rdn + nb8 * 8, nb16 * 16 - nb8 * 8, 0.0, s);
       if (err != hipSuccess) return err;
-      err = bf16 ? colgram_impl<BF16, 8, true>(X, ldx, m, n, rdn, gram8, cross8, partial, partial_cap, ctl, zero_cols, s)
-                 : colgram_impl<F32, 8, true>(X, ldx, m, n, rdn, gram8, cross8, partial, partial_cap, ctl, zero_cols, s);
+      err = colgram_impl<BF16, 8, true>(X, ldx, m, n, rdn, gram8, cross8, partial, partial_cap, ctl, zero_cols, s);
       if (err != hipSuccess) return err;
       const int64_t total = nb16 * 120;
       hipLaunchKernelGGL(k_gram16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, gram8, cross8, nb8, nb16,

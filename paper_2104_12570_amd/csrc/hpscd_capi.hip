@@ -160,14 +160,21 @@ struct Plan {
   int T, R, B, P, D;
 };
 
-hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hpscd_opts* o, Plan* pl) {
+// One planning attempt; `wide` selects the wide-block kernel (16 columns per
+// reduction).
+static hpscd_status plan_try(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hpscd_opts* o, bool wide,
+                             Plan* pl) {
   const int VEC = bf16 ? 8 : 4;
   bool grid;
   if (o->flags & HPSCD_F_FORCE_GRID) grid = true;
   else if (o->flags & HPSCD_F_FORCE_WG) grid = false;
   else grid = m > 256 * (bf16 ? 2 : 4) * VEC;
+  wide = wide && grid;
   std::vector<std::pair<int, int>> shapes;  // (T, R) candidates, smallest first
-  if (grid) {
+  if (wide) {
+    if (bf16) shapes = {{512, 1}};
+    else shapes = {{512, 2}, {256, 4}, {1024, 1}};
+  } else if (grid) {
     // FP32: the polling-wave kernel (kind 5) with 256 threads x 4 chunks first
     // (up to 256 workgroups, 1,048,576 rows), then the plain grid kernel
     if (bf16) shapes = {{1024, 1}, {512, 1}};
@@ -176,12 +183,6 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
   } else {
     if (bf16) shapes = {{256, 1}, {256, 2}};
     else shapes = {{256, 2}, {256, 4}};
-  }
-  // the wide-block kernel: 16 columns per reduction
-  const bool wide = grid && (o->depth == 8 || (o->depth == 0 && o->block == 16));
-  if (wide) {
-    if (bf16) shapes = {{512, 1}};
-    else shapes = {{512, 2}};
   }
   const int want = o->block > 0 ? o->block : (wide ? 16 : (grid ? 8 : 4));
   // Stop checks and refreshes fall at block starts, counted in column steps
@@ -205,7 +206,7 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
     return fail(HPSCD_EINVAL, "the pipelined kernel (depth 4) tests the stop rule only at sweep ends");
   if (o->depth != 0) kinds = {o->depth};
   else if (wide) kinds = {8};
-  else if (grid) kinds = {5, 2, 3};  // measured fastest on the 1M x 256 system; 4, 12, 13 are selectable
+  else if (grid) kinds = {5, 2, 3};  // 4, 6, 7, 12, 13 are selectable
   else kinds = {4, 3, 2};         // one workgroup: the deepest ring hides the most load latency
   auto kind_of = [&](int T, int R, int b) {
     for (int k : kinds)
@@ -233,6 +234,23 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
               grid ? "grid" : "workgroup", B);
 }
 
+hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hpscd_opts* o, Plan* pl) {
+  // The wide-block kernel when asked for; by default for FP32 grids, where it
+  // measured fastest from 100k to 1M rows (a reduction per 16 columns, none
+  // of the exchange's memory operations queued behind column loads), unless
+  // the block cannot be 16 (column checks, refreshes) or the grid would
+  // exceed 256 workgroups.
+  if (o->depth == 8 || (o->depth == 0 && o->block == 16)) return plan_try(c, m, n, bf16, o, true, pl);
+  if (o->depth == 0 && o->block == 0 && o->team_threads == 0 && !bf16) {
+    Plan wp;
+    if (plan_try(c, m, n, bf16, o, true, &wp) == HPSCD_OK && wp.grid) {
+      *pl = wp;
+      return HPSCD_OK;
+    }
+  }
+  return plan_try(c, m, n, bf16, o, false, pl);
+}
+
 // Wait between publishing a grid reduction's words and the first poll of
 // the others' words.  A poll that arrives before the slowest workgroup's
 // words are visible costs a second round trip (and, in the plain grid kernel,
@@ -242,7 +260,7 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
 uint32_t poll_delay_ticks(const Plan& pl) {
   if (!pl.grid) return 0;
   if (pl.D == 5 || pl.D == 6 || pl.D == 7) return (uint32_t)std::min(240.0, 80.0 + 0.6 * pl.P);
-  if (pl.D == 8) return (uint32_t)std::min(100.0, 0.2 * pl.P);  // no column loads in flight during the exchange
+  if (pl.D == 8) return (uint32_t)std::min(200.0, 0.6 * pl.P);
   if (pl.D == 2 || pl.D == 3) return (uint32_t)std::min(160.0, 0.65 * pl.P);
   return 0;
 }

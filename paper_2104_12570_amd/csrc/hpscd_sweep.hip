@@ -764,6 +764,11 @@ __global__ void __launch_bounds__(T) k_sweep_px(SolveArgs A) {
 // The barriers order LDS only (an LDS wait and s_barrier): a barrier with
 // memory fences would also wait for the column loads in flight.
 // Arithmetic, reduction order and stop logic are those of k_sweep.
+// First row of a chunk that holds only rows below m, read in place of a
+// chunk with no valid row (finite data, whose residual is held at zero).
+// With m below one chunk there is none: every chunk is then masked.
+__device__ inline int64_t full_chunk_row(int64_t m, int vec) { return m >= vec ? (m / vec - 1) * vec : 0; }
+
 __device__ inline void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   __builtin_amdgcn_s_barrier();
@@ -828,13 +833,16 @@ __global__ void __launch_bounds__(T) k_sweep_pe(SolveArgs A) {
   }
   const int64_t nblocks = A.blk_end - A.blk_begin;
   const int64_t col_bytes = A.ldx * (int64_t)(16 / VEC);
-  // Rows past m: a chunk with no valid row is read from the workgroup's first
-  // chunk instead (finite data; its residual is held at zero), and the one
-  // chunk of the system that straddles m is masked element by element.
+  // Rows past m: a chunk with no valid row is read from a chunk of valid
+  // rows instead (its residual is held at zero), and the one chunk of the
+  // system that straddles m is masked element by element (every chunk when
+  // m is below one chunk).
   const bool ragged = (int64_t)(wg + 1) * (T * R * VEC) > m;  // the workgroup holding the last rows
+  const bool tiny = m < VEC;
+  const int64_t safe_row = full_chunk_row(m, VEC);
   bool straddle[R];
 #pragma unroll
-  for (int c = 0; c < R; ++c) straddle[c] = __ballot(lim[c] > 0 && lim[c] < VEC) != 0;
+  for (int c = 0; c < R; ++c) straddle[c] = __ballot(lim[c] < VEC && (lim[c] > 0 || tiny)) != 0;
 
   // Partial sums of the block (B dots against the block-start residual and
   // ||e||^2) of this wave's rows, to LDS.
@@ -844,7 +852,7 @@ __global__ void __launch_bounds__(T) k_sweep_pe(SolveArgs A) {
       if (straddle[c]) {  // wave-uniform
 #pragma unroll
         for (int l = 0; l < B; ++l)
-          if (lim[c] > 0 && lim[c] < VEC) xl[l][c] = mask_chunk<S>(xl[l][c], lim[c]);
+          if (lim[c] < VEC && (lim[c] > 0 || tiny)) xl[l][c] = mask_chunk<S>(xl[l][c], lim[c]);
       }
     float p[NV];
 #pragma unroll
@@ -893,12 +901,12 @@ __global__ void __launch_bounds__(T) k_sweep_pe(SolveArgs A) {
     uint32_t boff[R];  // own rows (a chunk with no valid row reads the workgroup's first chunk)
 #pragma unroll
     for (int c = 0; c < R; ++c)
-      boff[c] = (uint32_t)((lim[c] > 0 ? wg_row0 + (int64_t)VEC * (tid + T * c) : wg_row0) * (16 / VEC));
+      boff[c] = (uint32_t)((lim[c] > 0 ? wg_row0 + (int64_t)VEC * (tid + T * c) : safe_row) * (16 / VEC));
     uint32_t boffp[R];  // the polling wave's rows, lane for lane (likewise)
 #pragma unroll
     for (int c = 0; c < R; ++c) {
       const int64_t r0 = wg_row0 + (int64_t)VEC * (NH * WAVE + lane + T * c);
-      boffp[c] = (uint32_t)((r0 < m ? r0 : wg_row0) * (16 / VEC));
+      boffp[c] = (uint32_t)((r0 < m ? r0 : safe_row) * (16 / VEC));
     }
     raw x0[B][R], x1[B][R], x2[D == 3 ? B : 1][R];
     raw q0[UPW], q1[UPW], q2[D == 3 ? UPW : 1];  // this wave's share of the poller's rows
@@ -1271,16 +1279,17 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
     const int64_t r0 = wg_row0 + (int64_t)VEC * (tid + T * c);
     const int64_t left = m - r0;
     lim[c] = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
-    // a chunk with no valid row reads the workgroup's first chunk (finite
-    // data; its residual is held at zero)
-    boff[c] = (uint32_t)((lim[c] > 0 ? r0 : wg_row0) * (16 / VEC));
+    // a chunk with no valid row reads a chunk of valid rows (its residual is
+    // held at zero)
+    boff[c] = (uint32_t)((lim[c] > 0 ? r0 : full_chunk_row(m, VEC)) * (16 / VEC));
 #pragma unroll
     for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? A.e0[r0 + i] : 0.f;
   }
   const bool ragged = wg_row0 + (T * R * VEC) > m;
+  const bool tiny = m < VEC;  // no chunk of valid rows: every chunk is masked
   bool straddle[R];
 #pragma unroll
-  for (int c = 0; c < R; ++c) straddle[c] = __ballot(lim[c] > 0 && lim[c] < VEC) != 0;
+  for (int c = 0; c < R; ++c) straddle[c] = __ballot(lim[c] < VEC && (lim[c] > 0 || tiny)) != 0;
 
   double prev_norm = A.fstat[1];
   const double ynorm = sqrt(*A.ynorm2);
@@ -1323,7 +1332,7 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
       if (straddle[c]) {  // wave-uniform
 #pragma unroll
         for (int l = 0; l < B; ++l)
-          if (lim[c] > 0 && lim[c] < VEC) x[l][c] = mask_chunk<S>(x[l][c], lim[c]);
+          if (lim[c] < VEC && (lim[c] > 0 || tiny)) x[l][c] = mask_chunk<S>(x[l][c], lim[c]);
       }
     // partial sums of this wave's rows
     float p[NV];
@@ -2365,7 +2374,7 @@ struct Variant {
 #define HPSCD_EENTRY(S, T, R, B, D) \
   {T, R, B, HPSCD_IS_BF16_##S, true, 4 + D, reinterpret_cast<const void*>(&k_sweep_pe<S, T, R, B, D>), T},
 // kind 8: wide blocks, no prefetch
-#define HPSCD_WIDE_VARIANTS(X_) X_(F32, 512, 2, 16) X_(BF16, 512, 1, 16)
+#define HPSCD_WIDE_VARIANTS(X_) X_(F32, 512, 2, 16) X_(BF16, 512, 1, 16) X_(F32, 256, 4, 16) X_(F32, 1024, 1, 16)
 #define HPSCD_WBENTRY(S, T, R, B) \
   {T, R, B, HPSCD_IS_BF16_##S, true, 8, reinterpret_cast<const void*>(&k_sweep_wide<S, T, R, B>), T},
 static const Variant kVariants[] = {HPSCD_SWEEP_VARIANTS(HPSCD_ENTRY) HPSCD_PIPE_VARIANTS(HPSCD_PENTRY)

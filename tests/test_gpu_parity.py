@@ -98,6 +98,18 @@ def test_ragged_shapes(lib, m, n):
         check(lib, s, 15, flags=flags)
 
 
+@pytest.mark.parametrize("m", [3, 4097, 8195])
+@pytest.mark.parametrize("kind", [5, 6, 7, 8])
+def test_grid_kinds_tiny_last_workgroup(lib, m, kind):
+    """Grids whose last workgroup holds fewer valid rows than one chunk (or
+    systems below one chunk), NaN padding rows: the chunks with no valid row
+    must not bring the padding in."""
+    say("tiny last workgroup", m, kind)
+    rng = np.random.default_rng(m + kind)
+    s = gen.make_system(rng, m, 21, noise=0.01, pad=np.nan)
+    check(lib, s, 6, flags=lib.F_FORCE_GRID, depth=kind, block=16 if kind == 8 else 8)
+
+
 def test_tall_grid_multi_wg(lib):
     """Several hundred thousand rows: a persistent grid of many workgroups."""
     s = gen.tall_large(m=300_001, n=40, seed=7, pad=np.nan)
