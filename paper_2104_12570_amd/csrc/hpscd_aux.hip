@@ -186,6 +186,38 @@ __global__ void __launch_bounds__(256) k_gram16(const double* gram8, const doubl
   gram16[b * 120 + q] = v;
 }
 
+// Step matrix of each 16-column block.  With D = diag(<X_l,X_l>) and L the
+// strictly lower in-block Gram, the block's sequential steps satisfy
+// (D + L) da = g for the dots g taken against the residual at the start of
+// the block (the forward substitution of the sweep kernels), so da = M g with
+// M = (D + L)^{-1}, lower triangular.  Column k of M is that substitution
+// applied to the unit vector e_k; a zero or padding column (reciprocal norm 0)
+// gives a zero row, i.e. da_l = 0 as in the substitution.  One thread per
+// (block, k); M of block b is row-major at minv[(b*16 + l)*16 + k].
+__global__ void __launch_bounds__(256) k_block_inverse16(const double* rdn, const double* gram, int64_t nb,
+                                                         double* minv) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= nb * 16) return;
+  const int64_t b = t / 16;
+  const int k = (int)(t % 16);
+  double x[16];
+#pragma unroll
+  for (int l = 0; l < 16; ++l) {
+    double acc = (l == k) ? 1.0 : 0.0;
+#pragma unroll
+    for (int i = 0; i < l; ++i) acc -= gram[b * 120 + l * (l - 1) / 2 + i] * x[i];
+    x[l] = acc * rdn[b * 16 + l];
+    minv[(b * 16 + l) * 16 + k] = x[l];
+  }
+}
+
+static hipError_t block_inverse16(const double* rdn, const double* gram, int64_t n, double* minv, hipStream_t s) {
+  const int64_t nb = (n + 15) / 16;
+  hipLaunchKernelGGL(k_block_inverse16, dim3((unsigned)((nb * 16 + 255) / 256)), dim3(256), 0, s, rdn, gram, nb,
+                     minv);
+  return hipGetLastError();
+}
+
 template <class S, int B, bool CROSS>
 static hipError_t colgram_impl(const void* X, int64_t ldx, int64_t m, int64_t n, double* rdn, double* gram,
                                double* cross, double* partial, int64_t partial_cap, int32_t* ctl,
@@ -262,9 +294,13 @@ hipError_t launch_colgram(const void* X, bool bf16, int64_t ldx, int64_t m, int6
       // FP32: one pass of the 16-column statistics.  BF16: the 16-column
       // tables from one pass of the 8-column statistics with the Gram of each
       // block against the previous one (cross must hold nb16 * 256 doubles:
-      // the 8-column cross Gram, then the 8-column in-block Gram).
-      if (!bf16) return colgram16_mfma<F32>(X, ldx, m, n, rdn, gram, partial, partial_cap, ctl, zero_cols, s);
+      // the 8-column cross Gram, then the 8-column in-block Gram).  Then the
+      // step matrices into cross.
       if (cross == nullptr) return hipErrorInvalidValue;
+      if (!bf16) {
+        hipError_t err = colgram16_mfma<F32>(X, ldx, m, n, rdn, gram, partial, partial_cap, ctl, zero_cols, s);
+        return err != hipSuccess ? err : block_inverse16(rdn, gram, n, cross, s);
+      }
       const int64_t nb8 = (n + 7) / 8, nb16 = (n + 15) / 16;
       double* cross8 = cross;
       double* gram8 = cross + nb8 * 64;
@@ -275,7 +311,8 @@ hipError_t launch_colgram(const void* X, bool bf16, int64_t ldx, int64_t m, int6
       const int64_t total = nb16 * 120;
       hipLaunchKernelGGL(k_gram16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, gram8, cross8, nb8, nb16,
                          gram);
-      return hipGetLastError();
+      err = hipGetLastError();
+      return err != hipSuccess ? err : block_inverse16(rdn, gram, n, cross, s);
     }
     default: return hipErrorInvalidValue;
   }

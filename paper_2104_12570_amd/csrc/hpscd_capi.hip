@@ -343,6 +343,7 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   A.rdn = c->rdn.as<double>();
   A.gram = c->gram.as<double>();
   A.cross = c->cross.as<double>();
+  A.minv = B == 16 ? c->cross.as<double>() : nullptr;
   A.a64 = c->a64.as<double>();
   A.e_out = c->eo.as<float>();
   A.hist = c->hist.as<double>();

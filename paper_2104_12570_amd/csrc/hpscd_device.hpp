@@ -80,6 +80,41 @@ __device__ inline float wave_sum(float v) {
   return (r0 + r1) + (r2 + r3);
 }
 
+// Wave sums of 16 values at once, scattered: lane L returns the total of
+// value (L >> 2) & 15 (the four lanes of a quad hold the same total).  Each
+// stage pairs every lane with a partner across one lane bit and halves the
+// values a lane holds (it keeps its half, adds the partner's copy of it), so
+// the 16 totals take 8 + 4 + 2 + 1 + 2 additions instead of 16 full sums.
+// Partners: lane xor 32 and xor 16 (LDS permute), then the row mirror (xor 15
+// within a row of 16), the half-row mirror (xor 7 within 8), xor 2 and xor 1.
+// The six masks are linearly independent over GF(2), so every lane's
+// contribution enters each total exactly once.  Fixed order.
+__device__ inline float wave_sum16_scatter(const float (&p)[16]) {
+  const int L = (int)__lane_id();
+  float q[8], r[4], s[2];
+  const bool h5 = (L & 32) != 0, h4 = (L & 16) != 0, h3 = (L & 8) != 0, h2 = (L & 4) != 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float keep = h5 ? p[i + 8] : p[i], send = h5 ? p[i] : p[i + 8];
+    q[i] = keep + __shfl_xor(send, 32);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float keep = h4 ? q[i + 4] : q[i], send = h4 ? q[i] : q[i + 4];
+    r[i] = keep + __shfl_xor(send, 16);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float keep = h3 ? r[i + 2] : r[i], send = h3 ? r[i] : r[i + 2];
+    s[i] = keep + dpp_f32<0x140>(send);  // row_mirror
+  }
+  const float keep = h2 ? s[1] : s[0], send = h2 ? s[0] : s[1];
+  float t = keep + dpp_f32<0x141>(send);  // row_half_mirror
+  t += dpp_f32<0x4E>(t);                  // quad_perm [2,3,0,1]
+  t += dpp_f32<0xB1>(t);                  // quad_perm [1,0,3,2]
+  return t;
+}
+
 template <int CTRL>
 __device__ inline double dpp_f64(double v) {
   const uint64_t u = (uint64_t)__double_as_longlong(v);

@@ -13,6 +13,7 @@ struct SolveArgs {
   const double* rdn;      // [nb*B] 1/<X_j,X_j> (0 for zero and padding columns)
   const double* gram;     // [nb][B*(B-1)/2] strictly-lower in-block Gram, (l,i) row-major
   const double* cross;    // [nb][B*B] Gram with the previous block (pipelined kernel only)
+  const double* minv;     // [nb][B][B] step matrix M = (D+L)^-1 of each block, row-major (B = 16 only)
   double* a64;            // [n] coefficients, accumulated in FP64
   float* e_out;           // [m] residual at exit
   double* hist;           // [max_sweeps+1] ||e||_2 after each complete sweep
@@ -89,6 +90,8 @@ bool batched_variant_exists(int B);
 
 // Column statistics: rdn = 1/<X_j,X_j> and the in-block Gram, FP64 sums.
 // cross: NULL, or [nb][B*B] receiving <X_{b,l}, X_{b-1,i}> at l*B + i (zero for b = 0).
+// B = 16: cross is required and receives each block's step matrix M (see
+// k_block_inverse16) instead.
 hipError_t launch_colgram(const void* X, bool bf16, int64_t ldx, int64_t m, int64_t n, int B,
                           double* rdn, double* gram, double* cross, double* partial, int64_t partial_cap,
                           int32_t* ctl, int64_t* zero_cols, hipStream_t s);

@@ -1249,8 +1249,12 @@ __global__ void __launch_bounds__(T) k_sweep_pe(SolveArgs A) {
 // takes less than two exchanges of 8-column blocks, each overlapped with the
 // next block's loads in the same CU memory pipeline.
 // The exchange is spread over the waves: value v of the block is polled and
-// summed by wave v mod NW.  Arithmetic and stop logic are those of k_sweep;
-// only the order of the fixed-order sums differs.
+// summed by wave v mod NW.  The block's B steps come from its step matrix
+// M = (D + L)^{-1} (precomputed, FP64): da = M g with g the grid-summed dots,
+// the same values as the forward substitution of k_sweep (only the rounding
+// order differs), but 16 independent FP64 dot products, one per lane,
+// instead of a serial chain run redundantly by every wave.  Stop logic is
+// that of k_sweep.
 template <class S, int T, int R, int B>
 __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
   using raw = typename S::raw_t;
@@ -1260,6 +1264,7 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
   constexpr int MAXC = 4;                      // up to 256 workgroups
   constexpr int VPW = (NV + NW - 1) / NW;      // values summed by one wave, at most
   constexpr long long TIMED_OUT = 0x7ff8000000000001ll;  // a NaN no arithmetic here produces
+  static_assert(B == 16, "the scattered wave sums and the step matrix rows are laid out for 16 columns");
   __shared__ float red[NW][NV];
   __shared__ double stot[NV];
 
@@ -1310,7 +1315,21 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
   };
 
   for (int64_t k = 0; k < nblocks; ++k) {
+    // (uniform; said explicitly so the column resource stays in scalar
+    // registers instead of a per-load loop over distinct values)
+    bi = __builtin_amdgcn_readfirstlane(bi);
     const int j0 = bi * B;
+    // row (lane mod B) of the block's step matrix M: da = M g
+    double mr[B];
+    {
+      const double2* src = reinterpret_cast<const double2*>(A.minv + ((int64_t)bi * B + (lane & (B - 1))) * B);
+#pragma unroll
+      for (int t = 0; t < B / 2; ++t) {
+        const double2 v = src[t];
+        mr[2 * t] = v.x;
+        mr[2 * t + 1] = v.y;
+      }
+    }
     // the block's columns (loads past the last column return zero)
     raw x[B][R];
     {
@@ -1325,8 +1344,6 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
         for (int c = 0; c < R; ++c)
           x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
     }
-    Coef<B> cf;
-    cf.load(A.rdn, A.gram, bi, lane);
 #pragma unroll
     for (int c = 0; c < R; ++c)
       if (straddle[c]) {  // wave-uniform
@@ -1334,29 +1351,28 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
         for (int l = 0; l < B; ++l)
           if (lim[c] < VEC && (lim[c] > 0 || tiny)) x[l][c] = mask_chunk<S>(x[l][c], lim[c]);
       }
-    // partial sums of this wave's rows
-    float p[NV];
-#pragma unroll
-    for (int l = 0; l < B; ++l) {
-      float acc = 0.f;
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(x[l][c], i), e[c][i], acc);
-      p[l] = acc;
-    }
+    // partial sums of this wave's rows: the B dots (summed over the wave
+    // with one scattered reduction) and ||e||^2
     {
-      float acc = 0.f;
+      float p[B];
+#pragma unroll
+      for (int l = 0; l < B; ++l) {
+        float acc = 0.f;
+#pragma unroll
+        for (int c = 0; c < R; ++c)
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(x[l][c], i), e[c][i], acc);
+        p[l] = acc;
+      }
+      float pn = 0.f;
 #pragma unroll
       for (int c = 0; c < R; ++c)
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) acc = fmaf(e[c][i], e[c][i], acc);
-      p[B] = acc;
-    }
-#pragma unroll
-    for (int l = 0; l < NV; ++l) {
-      const float v = wave_sum(p[l]);
-      if (lane == 0) red[wave][l] = v;
+        for (int i = 0; i < VEC; ++i) pn = fmaf(e[c][i], e[c][i], pn);
+      const float t = wave_sum16_scatter(p);
+      if ((lane & 3) == 0) red[wave][lane >> 2] = t;
+      const float tn = wave_sum(pn);
+      if (lane == 0) red[wave][B] = tn;
     }
     lds_barrier();
     // exchange with the grid: wave 0 publishes the workgroup's sums; value v
@@ -1433,18 +1449,13 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
       if (v < NV && lane == 0) stot[v] = any_timeout ? __longlong_as_double(TIMED_OUT) : tv;
     }
     lds_barrier();
-    double tot[NV];
-    bool tmo = false;  // some wave's poll timed out
-#pragma unroll
-    for (int l = 0; l < NV; ++l) {
-      tot[l] = uniform_f64(stot[l]);
-      tmo = tmo || (__double_as_longlong(tot[l]) == TIMED_OUT);
-    }
+    // some wave's poll timed out
+    const bool tmo = __ballot(lane < NV && __double_as_longlong(stot[lane < NV ? lane : 0]) == TIMED_OUT) != 0;
     if (tmo) {
       if (tid == 0) store_flag(&A.ctl[CTL_ERR], ERR_TIMEOUT);
       break;
     }
-    const double nrm2 = tot[B];
+    const double nrm2 = uniform_f64(stot[B]);
     const double nrm = sqrt(nrm2);
     if (!(nrm2 <= DBL_MAX)) {
       if (wg == 0 && tid == 0) store_flag(&A.ctl[CTL_ERR], aborting ? ERR_ABORTED : ERR_NONFINITE);
@@ -1467,11 +1478,15 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
         break;
       }
     }
-    double da[B];
-    forward_substitute<B>(tot, cf, da);
+    // da = M g: lane l of every wave computes da_l (fixed order), the axpy
+    // takes the B steps as scalars
+    double dl = 0.0;
+#pragma unroll
+    for (int q = 0; q < B; ++q) dl = fma(mr[q], stot[q], dl);
+    const int fl = __float_as_int((float)dl);
 #pragma unroll
     for (int l = 0; l < B; ++l) {
-      const float f = (float)da[l];
+      const float f = __int_as_float(__builtin_amdgcn_readlane(fl, l));
 #pragma unroll
       for (int c = 0; c < R; ++c)
 #pragma unroll
@@ -1483,14 +1498,10 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? e[c][i] : 0.f;
     }
-    if (tid < B) {
+    if (tid < B) {  // lane tid of wave 0 holds da_tid
       const int64_t j = j0 + tid;
-      if (j < n && (int)(j % A.P) == wg) {
-        double d = 0.0;
-#pragma unroll
-        for (int l = 0; l < B; ++l) if (tid == l) d = da[l];
-        (void)__hip_atomic_fetch_add(&A.a64[j], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      if (j < n && (int)(j % A.P) == wg)
+        (void)__hip_atomic_fetch_add(&A.a64[j], dl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     bi = (bi + 1 == nb) ? 0 : bi + 1;
     if (bi == 0) ++sdone;
