@@ -172,8 +172,10 @@ static hpscd_status plan_try(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, cons
   wide = wide && grid;
   std::vector<std::pair<int, int>> shapes;  // (T, R) candidates, smallest first
   if (wide) {
+    // FP32: the fewest rows per workgroup that keep the grid within 256
+    // workgroups (one per CU), so a smaller system still spreads over the chip
     if (bf16) shapes = {{512, 1}};
-    else shapes = {{512, 2}, {256, 4}, {1024, 1}};
+    else shapes = {{256, 1}, {512, 1}, {512, 2}, {256, 4}, {1024, 1}};
   } else if (grid) {
     // FP32: the polling-wave kernel (kind 5) with 256 threads x 4 chunks first
     // (up to 256 workgroups, 1,048,576 rows), then the plain grid kernel
@@ -260,7 +262,7 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
 uint32_t poll_delay_ticks(const Plan& pl) {
   if (!pl.grid) return 0;
   if (pl.D == 5 || pl.D == 6 || pl.D == 7) return (uint32_t)std::min(240.0, 80.0 + 0.6 * pl.P);
-  if (pl.D == 8) return (uint32_t)std::min(200.0, 0.6 * pl.P);
+  if (pl.D == 8) return (uint32_t)std::min(200.0, 65.0 + 0.22 * pl.P);
   if (pl.D == 2 || pl.D == 3) return (uint32_t)std::min(160.0, 0.65 * pl.P);
   return 0;
 }

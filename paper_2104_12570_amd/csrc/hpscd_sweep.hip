@@ -2385,7 +2385,8 @@ struct Variant {
 #define HPSCD_EENTRY(S, T, R, B, D) \
   {T, R, B, HPSCD_IS_BF16_##S, true, 4 + D, reinterpret_cast<const void*>(&k_sweep_pe<S, T, R, B, D>), T},
 // kind 8: wide blocks, no prefetch
-#define HPSCD_WIDE_VARIANTS(X_) X_(F32, 512, 2, 16) X_(BF16, 512, 1, 16) X_(F32, 256, 4, 16) X_(F32, 1024, 1, 16)
+#define HPSCD_WIDE_VARIANTS(X_) X_(F32, 512, 2, 16) X_(BF16, 512, 1, 16) X_(F32, 256, 4, 16) X_(F32, 1024, 1, 16) \
+  X_(F32, 512, 1, 16) X_(F32, 256, 1, 16)
 #define HPSCD_WBENTRY(S, T, R, B) \
   {T, R, B, HPSCD_IS_BF16_##S, true, 8, reinterpret_cast<const void*>(&k_sweep_wide<S, T, R, B>), T},
 static const Variant kVariants[] = {HPSCD_SWEEP_VARIANTS(HPSCD_ENTRY) HPSCD_PIPE_VARIANTS(HPSCD_PENTRY)

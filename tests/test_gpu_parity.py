@@ -154,6 +154,24 @@ def test_zero_columns_skipped(lib):
     assert r.a.cpu().numpy()[2] == 0.0
 
 
+@pytest.mark.parametrize("block,kind", [(16, 8), (8, 5)])
+def test_grid_zero_and_correlated_columns(lib, block, kind):
+    """Grid kernels on a system with zero columns and strongly correlated
+    neighbours inside one column block: the block's steps (forward
+    substitution, or its precomputed inverse for 16-column blocks) skip the
+    zero columns and follow the sequential steps of Algorithm 1."""
+    rng = np.random.default_rng(31)
+    s = gen.make_system(rng, 100_003, 40, noise=0.01, pad=np.nan)
+    s.Xt[[2, 7, 19], :] = 0.0
+    s.Xt[5, :s.m] = 0.99 * s.Xt[4, :s.m] + 0.1 * s.Xt[6, :s.m]
+    s.Xt[33, :s.m] = -s.Xt[32, :s.m] + 0.05 * s.Xt[34, :s.m]
+    say("zero and correlated columns", kind)
+    r, ref = check(lib, s, 8, flags=lib.F_FORCE_GRID, depth=kind, block=block)
+    assert r.info["kernel_kind"] == kind and r.info["team_wgs"] > 1
+    assert r.info["zero_cols"] == 3 and ref.zero_cols == 3
+    assert np.all(r.a.cpu().numpy()[[2, 7, 19]] == 0.0)
+
+
 def test_warm_start_resume(lib):
     """a0 = result of k sweeps, k more sweeps == 2k sweeps (to tolerance)."""
     s = gen.tall_small()
@@ -247,6 +265,19 @@ def test_grid_kernel_kinds_match_oracle(lib, block, kind):
     say("grid kind", block, kind)
     r, ref = check(lib, s, 6, block=block, depth=kind)
     assert r.info["block_used"] == block and r.info["team_wgs"] > 1
+
+
+@pytest.mark.parametrize("m,team_threads", [(250_007, 256), (500_009, 512), (1_000_003, 512)])
+def test_wide_kernel_default_shapes(lib, m, team_threads):
+    """The default FP32 grid kernel (16-column blocks) takes the fewest rows
+    per workgroup that keep the grid within 256 workgroups: 1024 rows per
+    workgroup up to ~262k rows, 2048 up to ~524k, then 4096.  Each shape
+    follows Algorithm 1 on a ragged system."""
+    s = gen.tall_large(m=m, n=37, seed=17, pad=np.nan)
+    say("wide default shape", m)
+    r, ref = check(lib, s, 4)
+    assert r.info["kernel_kind"] == 8 and r.info["team_threads"] == team_threads
+    assert 200 < r.info["team_wgs"] <= 256
 
 
 def test_pipelined_grid_stop_rule(lib):
