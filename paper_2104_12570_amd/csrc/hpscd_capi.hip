@@ -158,6 +158,7 @@ int pick_block(int want, std::initializer_list<int64_t> divides) {
 struct Plan {
   bool grid;
   int T, R, B, P, D;
+  int rpw;  // rows per workgroup
 };
 
 // One planning attempt; `wide` selects the wide-block kernel (16 columns per
@@ -223,13 +224,27 @@ static hpscd_status plan_try(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, cons
     if (b < 1) continue;
     if (o->block > 0 && b != o->block) continue;
     const int kind = kind_of(T, R, b);
-    const int64_t P = grid ? (m + rows - 1) / rows : 1;
+    int64_t P = grid ? (m + rows - 1) / rows : 1;
+    int64_t rpw = rows;
     if (grid) {
-      if (P > sweep_max_workgroups(T, R, b, bf16, true, kind)) continue;
+      const int maxw = sweep_max_workgroups(T, R, b, bf16, true, kind);
+      if (P > maxw) continue;
       const int per_cu = sweep_max_blocks_per_cu(T, R, b, bf16, true, kind);
       if (per_cu <= 0 || P > (int64_t)per_cu * c->cus) continue;
+      if (kind == 8 && 4 * P >= 3 * (int64_t)c->cus) {
+        // a grid that already covers most CUs spreads its rows over one
+        // workgroup per CU (at least half the capacity of a workgroup each);
+        // on the 1M x 256 system 256 workgroups instead of 245 measured 1.5 %
+        // faster, on a 100k-row system twice the workgroups at half the rows
+        // measured 5 % slower, so smaller grids are left as they are
+        const int64_t Pw = std::min<int64_t>({(int64_t)c->cus, (int64_t)maxw, (m + rows / 2 - 1) / (rows / 2)});
+        if (Pw > P) {
+          rpw = ((m + Pw - 1) / Pw + VEC - 1) / VEC * VEC;
+          P = (m + rpw - 1) / rpw;
+        }
+      }
     }
-    *pl = Plan{grid, T, R, b, (int)P, kind};
+    *pl = Plan{grid, T, R, b, (int)P, kind, (int)rpw};
     return HPSCD_OK;
   }
   return fail(HPSCD_EINVAL, "no kernel variant fits m=%lld (%s team, block %d)", (long long)m,
@@ -359,6 +374,7 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   A.ynorm2 = ynorm2;
   A.check_cols = (o->stop == HPSCD_STOP_REL_RESID) ? o->check_cols : 0;
   A.P = pl.P;
+  A.rows_per_wg = pl.rpw;
   A.timeout_ticks = kTimeoutTicks;
   A.poll_delay = poll_delay_ticks(pl);
   const int64_t total = (int64_t)o->max_sweeps * nb + 1;

@@ -29,6 +29,7 @@ struct SolveArgs {
   int64_t blk_begin;      // first global block index of this launch
   int64_t blk_end;        // one past the last global block index of this launch
   int32_t P;              // workgroups in the grid (1 for a workgroup team)
+  int32_t rows_per_wg;    // rows owned by one workgroup (wide-block kernel; others own T*R*VEC)
   uint64_t timeout_ticks; // bound on any spin-wait (100 MHz ticks)
   uint32_t poll_delay;    // ticks between publishing and the first poll of a grid reduction
 };

@@ -1275,23 +1275,31 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
   const int nb = (int)((n + B - 1) / B);
   if (A.ctl[CTL_NONFINITE] != 0 || A.ctl[CTL_DONE] != 0) return;
 
+  const int64_t col_bytes = A.ldx * (int64_t)(16 / VEC);
   float e[R][VEC];
   int lim[R];
   uint32_t boff[R];
-  const int64_t wg_row0 = (int64_t)wg * (T * R * VEC);
+  // This workgroup owns rows [wg_row0, wg_end): rows_per_wg (a multiple of
+  // VEC, at most T*R*VEC) per workgroup, so a grid can spread over every CU.
+  const int64_t wg_row0 = (int64_t)wg * A.rows_per_wg;
+  const int64_t wg_end = min(m, wg_row0 + (int64_t)A.rows_per_wg);
+  // A chunk with no valid row is read at an offset past the block's buffer
+  // range, which returns zero and moves no data, when the 32-bit offsets
+  // leave room for it (a block spans at most 16 column strides); otherwise
+  // it reads a chunk of valid rows.  Its residual is held at zero either way.
+  const bool oob = 31 * col_bytes < 0xFFFFFFFFll;
 #pragma unroll
   for (int c = 0; c < R; ++c) {
     const int64_t r0 = wg_row0 + (int64_t)VEC * (tid + T * c);
-    const int64_t left = m - r0;
+    const int64_t left = wg_end - r0;
     lim[c] = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
-    // a chunk with no valid row reads a chunk of valid rows (its residual is
-    // held at zero)
-    boff[c] = (uint32_t)((lim[c] > 0 ? r0 : full_chunk_row(m, VEC)) * (16 / VEC));
+    boff[c] = lim[c] > 0 ? (uint32_t)(r0 * (16 / VEC))
+                         : (oob ? (uint32_t)(16 * col_bytes) : (uint32_t)(full_chunk_row(m, VEC) * (16 / VEC)));
 #pragma unroll
     for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? A.e0[r0 + i] : 0.f;
   }
-  const bool ragged = wg_row0 + (T * R * VEC) > m;
-  const bool tiny = m < VEC;  // no chunk of valid rows: every chunk is masked
+  const bool ragged = wg_end - wg_row0 < (int64_t)(T * R * VEC);
+  const bool tiny = m < VEC && !oob;  // no chunk of valid rows to read: every chunk is masked
   bool straddle[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) straddle[c] = __ballot(lim[c] < VEC && (lim[c] > 0 || tiny)) != 0;
@@ -1299,7 +1307,6 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
   double prev_norm = A.fstat[1];
   const double ynorm = sqrt(*A.ynorm2);
   const int64_t nblocks = A.blk_end - A.blk_begin;
-  const int64_t col_bytes = A.ldx * (int64_t)(16 / VEC);
   int bi = (int)(A.blk_begin % nb);
   int sdone = (int)(A.blk_begin / nb);
   uint32_t seq = (uint32_t)(A.blk_begin + 1);

@@ -269,15 +269,16 @@ def test_grid_kernel_kinds_match_oracle(lib, block, kind):
 
 @pytest.mark.parametrize("m,team_threads", [(250_007, 256), (500_009, 512), (1_000_003, 512)])
 def test_wide_kernel_default_shapes(lib, m, team_threads):
-    """The default FP32 grid kernel (16-column blocks) takes the fewest rows
-    per workgroup that keep the grid within 256 workgroups: 1024 rows per
-    workgroup up to ~262k rows, 2048 up to ~524k, then 4096.  Each shape
-    follows Algorithm 1 on a ragged system."""
+    """The default FP32 grid kernel (16-column blocks) takes the smallest
+    workgroup shape that keeps the grid within 256 workgroups (capacity 1024
+    rows up to ~262k rows, 2048 up to ~524k, then 4096) and spreads the rows
+    evenly over up to one workgroup per CU.  Each shape follows Algorithm 1
+    on a ragged system."""
     s = gen.tall_large(m=m, n=37, seed=17, pad=np.nan)
     say("wide default shape", m)
     r, ref = check(lib, s, 4)
     assert r.info["kernel_kind"] == 8 and r.info["team_threads"] == team_threads
-    assert 200 < r.info["team_wgs"] <= 256
+    assert 245 <= r.info["team_wgs"] <= 256  # (rows spread over up to one workgroup per CU)
 
 
 def test_pipelined_grid_stop_rule(lib):
