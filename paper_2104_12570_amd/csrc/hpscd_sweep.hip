@@ -1237,6 +1237,17 @@ __global__ void __launch_bounds__(T) k_sweep_pe(SolveArgs A) {
   }
 }
 
+// The kernel's SolveArgs read again from the argument segment where they are
+// used, for fields needed only off the per-block path (stop tests, history,
+// control words): the pointer is opaque to the optimiser, so these loads are
+// not hoisted and the values do not occupy scalar registers across the loop.
+typedef const SolveArgs __attribute__((address_space(4)))* KArgs;
+__device__ inline KArgs cold_args() {
+  KArgs p = (KArgs)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
 // --------------------------------------------------------------------------
 // Grid kernel with wide blocks and no prefetch.
 //
@@ -1310,14 +1321,16 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
   int bi = (int)(A.blk_begin % nb);
   int sdone = (int)(A.blk_begin / nb);
   uint32_t seq = (uint32_t)(A.blk_begin + 1);
+  const bool col_checks = A.check_cols > 0 && A.stop == STOP_REL_RESID;
 
   auto finalize = [&](int sd, bool conv, int64_t cols, double nrm2) {
     if (wg == 0 && tid == 0) {
-      A.ctl[CTL_SWEEPS] = sd;
-      A.ctl[CTL_CONVERGED] = conv ? 1 : 0;
-      A.ctl[CTL_DONE] = 1;
-      A.ctl64[C64_COLS] = cols;
-      A.fstat[0] = nrm2;
+      const KArgs K = cold_args();
+      K->ctl[CTL_SWEEPS] = sd;
+      K->ctl[CTL_CONVERGED] = conv ? 1 : 0;
+      K->ctl[CTL_DONE] = 1;
+      K->ctl64[C64_COLS] = cols;
+      K->fstat[0] = nrm2;
     }
   };
 
@@ -1391,7 +1404,7 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
 #pragma unroll
       for (int w = 0; w < NW; ++w) sacc += red[w][lane];
       // a cancel request rides the norm of a sweep's first block as a NaN
-      if (lane == B && bi == 0 && wg == 0 && load_flag(&A.ctl[CTL_ABORT]) != 0) {
+      if (lane == B && bi == 0 && wg == 0 && load_flag(&cold_args()->ctl[CTL_ABORT]) != 0) {
         sacc = __int_as_float(0x7fc00000);
         injected = true;
       }
@@ -1459,28 +1472,30 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
     // some wave's poll timed out
     const bool tmo = __ballot(lane < NV && __double_as_longlong(stot[lane < NV ? lane : 0]) == TIMED_OUT) != 0;
     if (tmo) {
-      if (tid == 0) store_flag(&A.ctl[CTL_ERR], ERR_TIMEOUT);
+      if (tid == 0) store_flag(&cold_args()->ctl[CTL_ERR], ERR_TIMEOUT);
       break;
     }
     const double nrm2 = uniform_f64(stot[B]);
     const double nrm = sqrt(nrm2);
     if (!(nrm2 <= DBL_MAX)) {
-      if (wg == 0 && tid == 0) store_flag(&A.ctl[CTL_ERR], aborting ? ERR_ABORTED : ERR_NONFINITE);
+      if (wg == 0 && tid == 0) store_flag(&cold_args()->ctl[CTL_ERR], aborting ? ERR_ABORTED : ERR_NONFINITE);
       finalize(sdone, false, (int64_t)sdone * n + j0, nrm2);
       break;
     }
     if (bi == 0) {
-      if (wg == 0 && tid == 0) { A.hist[sdone] = nrm; A.fstat[1] = nrm; }
+      const KArgs K = cold_args();
+      if (wg == 0 && tid == 0) { K->hist[sdone] = nrm; K->fstat[1] = nrm; }
       bool stop = false, conv = false;
-      if (A.stop != STOP_NONE && nrm2 == 0.0) stop = conv = true;
-      else if (A.stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < A.tol * nrm) stop = conv = true;
-      else if (A.stop == STOP_REL_RESID && nrm < A.tol * ynorm) stop = conv = true;
-      if (!stop && sdone >= A.max_sweeps) stop = true;
+      if (K->stop != STOP_NONE && nrm2 == 0.0) stop = conv = true;
+      else if (K->stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < K->tol * nrm) stop = conv = true;
+      else if (K->stop == STOP_REL_RESID && nrm < K->tol * ynorm) stop = conv = true;
+      if (!stop && sdone >= K->max_sweeps) stop = true;
       prev_norm = nrm;
       if (stop) { finalize(sdone, conv, (int64_t)sdone * n, nrm2); break; }
-    } else if (A.check_cols > 0 && A.stop == STOP_REL_RESID) {
+    } else if (col_checks) {
+      const KArgs K = cold_args();
       const int64_t cols = (int64_t)sdone * n + j0;
-      if (cols % A.check_cols == 0 && (nrm2 == 0.0 || nrm < A.tol * ynorm)) {
+      if (cols % K->check_cols == 0 && (nrm2 == 0.0 || nrm < K->tol * ynorm)) {
         finalize(sdone, true, cols, nrm2);
         break;
       }
