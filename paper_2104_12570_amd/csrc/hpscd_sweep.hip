@@ -133,6 +133,7 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
   // block's first column: one 32-bit lane offset per chunk, one scalar offset
   // per column, and loads past the last column of the system return zero.
   auto load_cols = [&](raw (&x)[B][R], int bi) {
+    bi = __builtin_amdgcn_readfirstlane(bi);  // (uniform: keeps the resource in scalar registers)
     const int j0 = bi * B;
     const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
     const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
@@ -485,6 +486,7 @@ __global__ void __launch_bounds__(T) k_sweep_px(SolveArgs A) {
   Coef<B> c0, c1;
 
   auto rsrc = [&](int bi) {
+    bi = __builtin_amdgcn_readfirstlane(bi);  // (uniform: keeps the resource in scalar registers)
     const int j0 = bi * B;
     const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
     const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
@@ -1705,6 +1707,7 @@ __global__ void __launch_bounds__(T + WAVE) k_sweep_ws(SolveArgs A) {
   Coef<B> c0, c1, c2;
 
   auto load_block = [&](raw (&x)[B][R], Coef<B>& cf, int bi) {
+    bi = __builtin_amdgcn_readfirstlane(bi);  // (uniform: keeps the resource in scalar registers)
     const int j0 = bi * B;
     const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
     const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
@@ -1895,6 +1898,7 @@ __global__ void __launch_bounds__(T) k_sweep_pipe(SolveArgs A) {
   CF c0, c1, c2, c3;
 
   auto load_block = [&](raw (&x)[B][R], CF& cf, int bi) {
+    bi = __builtin_amdgcn_readfirstlane(bi);  // (uniform: keeps the resource in scalar registers)
     const int j0 = bi * B;
     const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
     const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
