@@ -108,7 +108,25 @@ __global__ void __launch_bounds__(256) k_colgram16_mfma(const void* X, int64_t l
     const int64_t col = b * B + j;
     typedef double d4 __attribute__((ext_vector_type(4)));
     d4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t row = r0; row < r1; row += 4 * VEC) {
+    int64_t row = r0;
+    // U row steps per round with all their loads issued first: one load in
+    // flight per wave leaves the matrix cores idle for most of each load's
+    // latency
+    constexpr int U = 8;
+    for (; row + U * 4 * VEC <= r1; row += U * 4 * VEC) {
+      raw xs[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        xs[u] = col < n ? load_chunk<S>(X, col * ldx + row + (int64_t)(u * 4 + kq) * VEC) : S::zero();
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < VEC; ++t) {
+          const double v = (double)chunk_at<S>(xs[u], t);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+        }
+    }
+    for (; row < r1; row += 4 * VEC) {
       const int64_t rr = row + (int64_t)kq * VEC;
       const int64_t left = r1 - rr;
       const int lim = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
