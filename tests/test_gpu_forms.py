@@ -274,3 +274,20 @@ def test_bf16_blocks_in_flight_kernel(lib, kind):
     assert r.info["refreshes"] == ref.refreshes
     assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
     assert np.all(np.abs(np.asarray(r.hist) - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0])
+
+
+def test_bf16_wide_kernel_spread_grid(lib):
+    """The storage form on the wide-block kernel with its rows spread over
+    one workgroup per CU (about 3,900 rows each, ragged last workgroup, NaN
+    padding rows), with refreshes, against the oracle of the form."""
+    s = gen.tall_large(m=1_000_003, n=32, seed=41, pad=np.nan)
+    X32 = dev(s.Xt)
+    Xb = lib.convert_bf16(X32)
+    say("bf16 wide spread")
+    r = lib.solve_bf16(Xb, X32, dev(s.y), max_sweeps=3, refresh_cols=32, block=16, depth=8,
+                       flags=lib.F_FORCE_GRID)
+    ref = oracle.solve_bf16_refresh(s.Xt, s.y, s.m, max_sweeps=3, refresh_cols=32)
+    assert r.info["kernel_kind"] == 8 and r.info["team_wgs"] > 245
+    assert r.info["refreshes"] == ref.refreshes
+    assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
+    assert np.all(np.abs(np.asarray(r.hist) - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0])
