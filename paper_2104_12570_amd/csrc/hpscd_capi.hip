@@ -170,7 +170,6 @@ static hpscd_status plan_try(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, cons
   if (o->flags & HPSCD_F_FORCE_GRID) grid = true;
   else if (o->flags & HPSCD_F_FORCE_WG) grid = false;
   else grid = m > 256 * (bf16 ? 2 : 4) * VEC;
-  wide = wide && grid;
   std::vector<std::pair<int, int>> shapes;  // (T, R) candidates, smallest first
   if (wide) {
     // FP32: the fewest rows per workgroup that keep the grid within 256

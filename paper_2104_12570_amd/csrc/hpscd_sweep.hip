@@ -1397,78 +1397,92 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
       if (lane == 0) red[wave][B] = tn;
     }
     lds_barrier();
-    // exchange with the grid: wave 0 publishes the workgroup's sums; value v
-    // is polled and summed by wave v mod NW
-    const uint64_t* slot_base = A.slots + (int64_t)(seq & 1u) * NV * A.P;
-    bool injected = false;
-    if (wave == 0 && lane < NV) {
-      float sacc = 0.f;
+    bool aborting = false;
+    if (A.P == 1) {
+      // one workgroup (a system of at most T*R*VEC rows): its sums are the
+      // totals, no exchange; a cancel request rides the norm as a NaN
+      if (tid < NV) {
+        double acc = 0.0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) sacc += red[w][lane];
-      // a cancel request rides the norm of a sweep's first block as a NaN
-      if (lane == B && bi == 0 && wg == 0 && load_flag(&cold_args()->ctl[CTL_ABORT]) != 0) {
-        sacc = __int_as_float(0x7fc00000);
-        injected = true;
+        for (int w = 0; w < NW; ++w) acc += (double)red[w][tid];
+        if (tid == B && bi == 0 && load_flag(&cold_args()->ctl[CTL_ABORT]) != 0)
+          acc = __longlong_as_double(0x7ff8000000000000ll);
+        stot[tid] = acc;
       }
-      publish(const_cast<uint64_t*>(slot_base) + (int64_t)lane * A.P + wg, seq, sacc);
-    }
-    const bool aborting = __ballot(injected) != 0;  // (meaningful in wave 0 of workgroup 0)
-    if (A.poll_delay) {
-      const uint64_t t0d = now_ticks();
-      while (now_ticks() - t0d < A.poll_delay) __builtin_amdgcn_s_sleep(2);
-    }
-    const int ncn = (A.P + WAVE - 1) / WAVE;
-    uint64_t w[VPW][MAXC];
-#pragma unroll
-    for (int q = 0; q < VPW; ++q) {
-      const int v = wave + NW * q;
-      const int vv = v < NV ? v : NV - 1;  // (rounds past the last value reread a valid word)
-#pragma unroll
-      for (int c = 0; c < MAXC; ++c) {
-        const int idx = c * WAVE + lane;
-        const bool live = c < ncn && idx < A.P;
-        w[q][c] = live ? peek(slot_base + (int64_t)vv * A.P + idx) : ((uint64_t)seq << 32);
+    } else {
+      // exchange with the grid: wave 0 publishes the workgroup's sums; value v
+      // is polled and summed by wave v mod NW
+      const uint64_t* slot_base = A.slots + (int64_t)(seq & 1u) * NV * A.P;
+      bool injected = false;
+      if (wave == 0 && lane < NV) {
+        float sacc = 0.f;
+  #pragma unroll
+        for (int w = 0; w < NW; ++w) sacc += red[w][lane];
+        // a cancel request rides the norm of a sweep's first block as a NaN
+        if (lane == B && bi == 0 && wg == 0 && load_flag(&cold_args()->ctl[CTL_ABORT]) != 0) {
+          sacc = __int_as_float(0x7fc00000);
+          injected = true;
+        }
+        publish(const_cast<uint64_t*>(slot_base) + (int64_t)lane * A.P + wg, seq, sacc);
       }
-    }
-    uint64_t tstart = 0;
-    bool timed_out = false;
-    for (int spin = 0;; ++spin) {
-      bool ready = true;
-#pragma unroll
-      for (int q = 0; q < VPW; ++q)
-#pragma unroll
-        for (int c = 0; c < MAXC; ++c) ready = ready && ((uint32_t)(w[q][c] >> 32) == seq);
-      if (ready) break;
-      if (spin == 0) tstart = now_ticks();
-      else if (now_ticks() - tstart > A.timeout_ticks) {
-        timed_out = true;
-        break;
+      aborting = __ballot(injected) != 0;  // (meaningful in wave 0 of workgroup 0)
+      if (A.poll_delay) {
+        const uint64_t t0d = now_ticks();
+        while (now_ticks() - t0d < A.poll_delay) __builtin_amdgcn_s_sleep(2);
       }
-      __builtin_amdgcn_s_sleep(1);
-#pragma unroll
+      const int ncn = (A.P + WAVE - 1) / WAVE;
+      uint64_t w[VPW][MAXC];
+  #pragma unroll
       for (int q = 0; q < VPW; ++q) {
         const int v = wave + NW * q;
-        const int vv = v < NV ? v : NV - 1;
-#pragma unroll
+        const int vv = v < NV ? v : NV - 1;  // (rounds past the last value reread a valid word)
+  #pragma unroll
         for (int c = 0; c < MAXC; ++c) {
           const int idx = c * WAVE + lane;
-          if ((uint32_t)(w[q][c] >> 32) != seq) w[q][c] = peek(slot_base + (int64_t)vv * A.P + idx);
+          const bool live = c < ncn && idx < A.P;
+          w[q][c] = live ? peek(slot_base + (int64_t)vv * A.P + idx) : ((uint64_t)seq << 32);
         }
       }
-    }
-    const bool any_timeout = __ballot(timed_out) != 0;
-    // fixed order: per lane over its chunks, then across the lanes
-#pragma unroll
-    for (int q = 0; q < VPW; ++q) {
-      const int v = wave + NW * q;
-      double acc = 0.0;
-#pragma unroll
-      for (int c = 0; c < MAXC; ++c) {
-        const int idx = c * WAVE + lane;
-        acc += (c < ncn && idx < A.P) ? (double)__uint_as_float((uint32_t)w[q][c]) : 0.0;
+      uint64_t tstart = 0;
+      bool timed_out = false;
+      for (int spin = 0;; ++spin) {
+        bool ready = true;
+  #pragma unroll
+        for (int q = 0; q < VPW; ++q)
+  #pragma unroll
+          for (int c = 0; c < MAXC; ++c) ready = ready && ((uint32_t)(w[q][c] >> 32) == seq);
+        if (ready) break;
+        if (spin == 0) tstart = now_ticks();
+        else if (now_ticks() - tstart > A.timeout_ticks) {
+          timed_out = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+  #pragma unroll
+        for (int q = 0; q < VPW; ++q) {
+          const int v = wave + NW * q;
+          const int vv = v < NV ? v : NV - 1;
+  #pragma unroll
+          for (int c = 0; c < MAXC; ++c) {
+            const int idx = c * WAVE + lane;
+            if ((uint32_t)(w[q][c] >> 32) != seq) w[q][c] = peek(slot_base + (int64_t)vv * A.P + idx);
+          }
+        }
       }
-      const double tv = wave_sum(acc);
-      if (v < NV && lane == 0) stot[v] = any_timeout ? __longlong_as_double(TIMED_OUT) : tv;
+      const bool any_timeout = __ballot(timed_out) != 0;
+      // fixed order: per lane over its chunks, then across the lanes
+  #pragma unroll
+      for (int q = 0; q < VPW; ++q) {
+        const int v = wave + NW * q;
+        double acc = 0.0;
+  #pragma unroll
+        for (int c = 0; c < MAXC; ++c) {
+          const int idx = c * WAVE + lane;
+          acc += (c < ncn && idx < A.P) ? (double)__uint_as_float((uint32_t)w[q][c]) : 0.0;
+        }
+        const double tv = wave_sum(acc);
+        if (v < NV && lane == 0) stot[v] = any_timeout ? __longlong_as_double(TIMED_OUT) : tv;
+      }
     }
     lds_barrier();
     // some wave's poll timed out
@@ -1480,7 +1494,10 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
     const double nrm2 = uniform_f64(stot[B]);
     const double nrm = sqrt(nrm2);
     if (!(nrm2 <= DBL_MAX)) {
-      if (wg == 0 && tid == 0) store_flag(&cold_args()->ctl[CTL_ERR], aborting ? ERR_ABORTED : ERR_NONFINITE);
+      if (wg == 0 && tid == 0) {
+        const bool ab = aborting || (A.P == 1 && load_flag(&cold_args()->ctl[CTL_ABORT]) != 0);
+        store_flag(&cold_args()->ctl[CTL_ERR], ab ? ERR_ABORTED : ERR_NONFINITE);
+      }
       finalize(sdone, false, (int64_t)sdone * n + j0, nrm2);
       break;
     }
@@ -2415,9 +2432,12 @@ struct Variant {
   X_(F32, 512, 1, 16) X_(F32, 256, 1, 16)
 #define HPSCD_WBENTRY(S, T, R, B) \
   {T, R, B, HPSCD_IS_BF16_##S, true, 8, reinterpret_cast<const void*>(&k_sweep_wide<S, T, R, B>), T},
+#define HPSCD_WB1ENTRY(S, T, R, B) \
+  {T, R, B, HPSCD_IS_BF16_##S, false, 8, reinterpret_cast<const void*>(&k_sweep_wide<S, T, R, B>), T},
 static const Variant kVariants[] = {HPSCD_SWEEP_VARIANTS(HPSCD_ENTRY) HPSCD_PIPE_VARIANTS(HPSCD_PENTRY)
                                         HPSCD_WS_VARIANTS(HPSCD_WENTRY) HPSCD_PX_VARIANTS(HPSCD_XENTRY)
-                                            HPSCD_PE_VARIANTS(HPSCD_EENTRY) HPSCD_WIDE_VARIANTS(HPSCD_WBENTRY)};
+                                            HPSCD_PE_VARIANTS(HPSCD_EENTRY) HPSCD_WIDE_VARIANTS(HPSCD_WBENTRY)
+                                            HPSCD_WIDE_VARIANTS(HPSCD_WB1ENTRY)};
 
 // The deepest prefetch ring built for the shape (D = 0: any).
 static const Variant* find_variant(int T, int R, int B, bool bf16, bool grid, int D = 0) {

@@ -291,3 +291,19 @@ def test_bf16_wide_kernel_spread_grid(lib):
     assert r.info["refreshes"] == ref.refreshes
     assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
     assert np.all(np.abs(np.asarray(r.hist) - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0])
+
+
+def test_bf16_wide_kernel_one_workgroup(lib):
+    """The storage form on the single-workgroup wide-block kernel (a short
+    wide system), with refreshes, against the oracle of the form."""
+    rng = np.random.default_rng(43)
+    s = gen.make_system(rng, 2000, 480, noise=0.01, pad=np.nan)
+    X32 = dev(s.Xt)
+    Xb = lib.convert_bf16(X32)
+    say("bf16 wide one workgroup")
+    r = lib.solve_bf16(Xb, X32, dev(s.y), max_sweeps=3, refresh_cols=160, block=16, depth=8)
+    ref = oracle.solve_bf16_refresh(s.Xt, s.y, s.m, max_sweeps=3, refresh_cols=160)
+    assert r.info["kernel_kind"] == 8 and r.info["team_wgs"] == 1
+    assert r.info["refreshes"] == ref.refreshes
+    assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
+    assert np.all(np.abs(np.asarray(r.hist) - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0])

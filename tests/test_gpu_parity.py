@@ -281,6 +281,31 @@ def test_wide_kernel_default_shapes(lib, m, team_threads):
     assert 245 <= r.info["team_wgs"] <= 256  # (rows spread over up to one workgroup per CU)
 
 
+@pytest.mark.parametrize("m,n", [(2000, 200), (1500, 37), (700, 64), (4000, 48), (5, 20)])
+def test_wide_kernel_one_workgroup(lib, m, n):
+    """The wide-block kernel as a single workgroup (no grid exchange: the
+    workgroup's sums are the totals), 16-column blocks through the step
+    matrix, n not always a multiple of 16, NaN padding rows."""
+    rng = np.random.default_rng(m + n)
+    s = gen.make_system(rng, m, n, noise=0.01, pad=np.nan)
+    say("wide one workgroup", m, n)
+    r, ref = check(lib, s, 12, block=16, depth=8)
+    assert r.info["kernel_kind"] == 8 and r.info["team_wgs"] == 1
+
+
+def test_wide_kernel_one_workgroup_resid_stop(lib):
+    """The single-workgroup wide kernel stops at a column check inside a
+    sweep where the oracle does."""
+    s = gen.tall_small(n=48, pad=np.nan)
+    say("wide one workgroup resid stop")
+    kw = dict(stop=lib.STOP_REL_RESID, tol=0.01, check_cols=16)
+    r = lib.solve(dev(s.Xt), dev(s.y), max_sweeps=50, block=16, depth=8, **kw)
+    ref = oracle.solve(s.Xt, s.y, s.m, max_sweeps=50, stop=oracle.STOP_REL_RESID, tol=0.01, check_cols=16)
+    assert r.info["kernel_kind"] == 8 and r.info["team_wgs"] == 1
+    assert r.info["converged"] == 1 and r.info["cols_done"] == ref.cols
+    assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
+
+
 def test_pipelined_grid_stop_rule(lib):
     s = gen.tall_large(m=250_000, n=48, seed=21)
     say("pipelined stop")
