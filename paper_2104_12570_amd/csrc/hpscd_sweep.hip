@@ -2224,16 +2224,27 @@ __device__ inline void team_solve(const BatchArgs& A, int sidx, int ttid, float 
   const double* gram = A.gram + sd.g_off / B * Coef<B>::NG;
   double* hist = A.hist + sd.h_off;
 
+  // Columns are read through a buffer resource based at the block's first
+  // column (built from values equal across the team, made explicitly
+  // uniform so the resource stays in scalar registers).  Every load is
+  // issued unconditionally, so the compiler can wait for the current block
+  // with an exact count while the next one is in flight: a chunk with no
+  // valid row is read past the block's range (zero, no data moved) when the
+  // 32-bit offsets leave room, else at row 0; columns past n lie past the
+  // range too; partly or wholly invalid chunks are masked before use.
+  const uint32_t col_bytes = (uint32_t)__builtin_amdgcn_readfirstlane((int)(sd.ldx * 4));
+  const bool oob = (int64_t)(2 * B) * sd.ldx * 4 < 0xFFFFFFFFll;
   float e[R][VEC];
   int lim[R];
-  int64_t rof[R];
+  uint32_t boff[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) {
-    rof[c] = (int64_t)VEC * (ttid + TT * c);
-    const int64_t left = m - rof[c];
+    const int64_t rof = (int64_t)VEC * (ttid + TT * c);
+    const int64_t left = m - rof;
     lim[c] = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
+    boff[c] = lim[c] > 0 ? (uint32_t)(rof * 4) : (oob ? (uint32_t)B * col_bytes : 0u);
 #pragma unroll
-    for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? A.e0pool[sd.y_off + rof[c] + i] : 0.f;
+    for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? A.e0pool[sd.y_off + rof + i] : 0.f;
   }
   const double ynorm = sqrt(A.ynorm2[sidx]);
   double prev_norm = 0.0;
@@ -2243,22 +2254,27 @@ __device__ inline void team_solve(const BatchArgs& A, int sidx, int ttid, float 
 
   auto load_block = [&](raw (&x)[B][R], Coef<B>& cf, int64_t k) {
     const int64_t bi = k % nb, j0 = bi * B;
+    const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
+    const int64_t span = (int64_t)nvalid * sd.ldx * 4;
+    const uint64_t base = (uint64_t)(X + j0 * sd.ldx);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(base >> 32));
+    const uint32_t nrec = (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)(span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span));
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), 0, (int)nrec, 0x00020000);
 #pragma unroll
-    for (int l = 0; l < B; ++l) {
-      const int64_t j = j0 + l;
+    for (int l = 0; l < B; ++l)
 #pragma unroll
-      for (int c = 0; c < R; ++c) {
-        if (j < n && lim[c] > 0) x[l][c] = load_chunk<S>(X, j * sd.ldx + rof[c]);
-        else x[l][c] = S::zero();
-      }
-    }
+      for (int c = 0; c < R; ++c)
+        x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
     cf.load(rdn, gram, bi, lane);
   };
 
   auto step = [&](raw (&cur)[B][R], raw (&nxt)[B][R], Coef<B>& ccur, Coef<B>& cnxt, int64_t k) -> bool {
     const int64_t bi = k % nb, j0 = bi * B;
     const int sdone = (int)(k / nb);
-    if (k + 1 < ke) load_block(nxt, cnxt, k + 1);
+    load_block(nxt, cnxt, k + 1);  // (past the last step: a harmless reread, issued so every path loads alike)
     float p[NV];
 #pragma unroll
     for (int l = 0; l < B; ++l) {
