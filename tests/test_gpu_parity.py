@@ -375,3 +375,34 @@ def test_blocks_in_flight_kernel(lib, kind, team_threads, m, n, stop):
     else:
         assert r.info["cols_done"] == ref.cols and ref.cols % n != 0  # a check inside a sweep
         assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
+
+
+@pytest.mark.parametrize("m,n,kw", [(1_000_000, 256, {}), (2000, 512, dict(block=16, depth=8))])
+def test_abort_from_another_thread(lib, m, n, kw):
+    """hpscd_abort from a second host thread ends a running solve at the next
+    sweep start with EABORTED (the grid kernel, and the wide-block kernel as
+    one workgroup); the solve is bounded (4000 sweeps), so a missed request
+    shows as a failure, not a hang."""
+    import threading
+    import time
+    import torch
+    rng = np.random.default_rng(m + n)
+    s = gen.make_system(rng, m, n, noise=0.01)
+    X, y = dev(s.Xt), dev(s.y)
+    torch.cuda.synchronize()
+    say("abort", m, n)
+    box = {}
+
+    def run():
+        try:
+            box["r"] = lib.solve(X, y, max_sweeps=4000, **kw)
+        except lib.HPSCDError as ex:
+            box["e"] = ex
+
+    t = threading.Thread(target=run)
+    t.start()
+    time.sleep(0.15)
+    lib.abort()
+    t.join(120)
+    assert not t.is_alive()
+    assert "e" in box and box["e"].status == lib.EABORTED, box
