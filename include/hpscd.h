@@ -70,7 +70,8 @@ typedef struct {
   int64_t refresh_cols; /* bf16 form: e = y - X32·a (FP64 sums) every refresh_cols column steps; 0 = never */
   int32_t block;        /* columns per reduction round (1, 2, 4, 8, or 16 with depth 8); 0 = library choice */
   int32_t flags;        /* HPSCD_F_* */
-  int32_t team_threads; /* threads per workgroup; 0 = library choice */
+  int32_t team_threads; /* threads per workgroup; 0 = library choice.  Batched calls: 256
+                           (four waves, eight chunks per thread) or 512 (eight waves, four) */
   int32_t depth;        /* kernel kind; 0 = library choice.  2, 3: prefetch ring of 2 or 3 blocks;
                            4: pipelined grid kernel, or a 4-block ring for one workgroup;
                            5: grid kernel whose polling waves never wait behind column loads

@@ -78,7 +78,7 @@ constexpr uint64_t kTimeoutTicks = 1000000000ull;  // 10 s of the 100 MHz clock
 
 struct Tuned {
   int B;
-  int64_t wave_max_m;  // systems with m <= this go four to a workgroup, one per wave
+  int64_t wave_max_m;  // systems with m <= this share a workgroup, one per wave
 };
 
 // Device workspace of one batched solve (the context's, or a plan's own).
@@ -615,7 +615,7 @@ hpscd_status validate_batch(int32_t count, const hpscd_sys* sys, const float* Xp
   if (!sys) return fail(HPSCD_EINVAL, "sys is NULL");
   if (!Xpool || !ypool || !apool) return fail(HPSCD_EINVAL, "NULL pool");
   if (!aligned16(Xpool)) return fail(HPSCD_EINVAL, "Xpool must be 16-byte aligned");
-  const int64_t max_m = batched_rows_per_wg();
+  const int64_t max_m = batched_rows_per_wg(1);  // (every shape holds 8192 rows)
   for (int32_t i = 0; i < count; ++i) {
     const hpscd_sys& s = sys[i];
     if (s.m < 1 || s.n < 1) return fail(HPSCD_EINVAL, "system %d: m and n must be >= 1", i);
@@ -629,10 +629,12 @@ hpscd_status validate_batch(int32_t count, const hpscd_sys* sys, const float* Xp
 }
 
 // Work items in longest-processing-time order: systems that fit one wave are
-// grouped four to an item by decreasing size; larger systems get a whole
-// workgroup.  The queue hands items out in this order.
-void plan_batch(int32_t count, const hpscd_sys* sys, int B, int64_t wave_max_m, int hist_len, double tol,
+// grouped as many to an item as the workgroup has waves, by decreasing size;
+// larger systems get a whole workgroup.  The queue hands items out in this
+// order.  `code` names the kernel variant (block size and shape).
+void plan_batch(int32_t count, const hpscd_sys* sys, int code, int64_t wave_max_m, int hist_len, double tol,
                 BatchPlan* bp) {
+  const int B = batched_block(code);
   bp->sd.resize(count);
   bp->blk_first.resize(count);
   int64_t g = 0, blk = 0;
@@ -650,17 +652,17 @@ void plan_batch(int32_t count, const hpscd_sys* sys, int B, int64_t wave_max_m, 
   bp->rdn_size = g;
   bp->gram_size = g / B * (B * (B - 1) / 2);
   std::vector<int32_t> small, big;
-  const int64_t wave_rows = std::min<int64_t>(wave_max_m, batched_rows_per_wave());
+  const int64_t wave_rows = std::min<int64_t>(wave_max_m, batched_rows_per_wave(code));
   for (int32_t i = 0; i < count; ++i) (sys[i].m <= wave_rows ? small : big).push_back(i);
   auto work = [&](int32_t i) { return (double)sys[i].m * (double)sys[i].n; };
   auto by_work = [&](int32_t a, int32_t b) { return work(a) > work(b); };
   std::sort(small.begin(), small.end(), by_work);
   std::sort(big.begin(), big.end(), by_work);
   std::vector<std::pair<double, WorkItem>> items;
-  for (int32_t i : big) items.push_back({work(i), WorkItem{0, 1, {i, 0, 0, 0}}});
-  const int per = batched_threads() / WAVE;
+  for (int32_t i : big) items.push_back({work(i), WorkItem{0, 1, {i}}});
+  const int per = std::min<int>(batched_threads(code) / WAVE, (int)(sizeof(WorkItem::sys) / sizeof(int32_t)));
   for (size_t k = 0; k < small.size(); k += per) {
-    WorkItem w{1, 0, {0, 0, 0, 0}};
+    WorkItem w{1, 0, {}};
     for (int q = 0; q < per && k + q < small.size(); ++q) w.sys[w.count++] = small[k + q];
     items.push_back({work(small[k]), w});
   }
@@ -750,7 +752,7 @@ hpscd_status enqueue_batch(hpscd_ctx* c, BatchWork& w, const BatchPlan& bp, cons
     HIP_TRY(launch_residual_batched(Xpool, ypool, dsys, count, nullptr, a0pool, w.e0.as<float>(), nullptr, st));
     e0 = w.e0.as<float>();
   }
-  HIP_TRY(launch_colgram_batched(Xpool, dsys, count, bp.nblk, w.blk.as<int64_t>(), B, w.rdn.as<double>(),
+  HIP_TRY(launch_colgram_batched(Xpool, dsys, count, bp.nblk, w.blk.as<int64_t>(), batched_block(B), w.rdn.as<double>(),
                                  w.gram.as<double>(), ctl + CTL_NONFINITE, st));
   if (ev) HIP_TRY(hipEventRecord(ev[1], st));
   BatchArgs A{};
@@ -818,9 +820,9 @@ hpscd_status collect_batch(hpscd_ctx* c, BatchWork& w, const BatchLayout& L, con
     info->sweeps_done = (int32_t)std::min<int64_t>(swsum, INT32_MAX);
     info->converged = (int32_t)cvsum;
     info->cols_done = cols;
-    info->block_used = B;
+    info->block_used = batched_block(B);
     info->team_wgs = grid;
-    info->team_threads = batched_threads();
+    info->team_threads = batched_threads(B);
     info->sweep_ms = ev ? elapsed(ev[1], ev[2]) : std::numeric_limits<double>::quiet_NaN();
     info->total_ms = ev ? elapsed(ev[0], ev[3]) : std::numeric_limits<double>::quiet_NaN();
     info->final_rel_resid = std::numeric_limits<double>::quiet_NaN();
@@ -850,8 +852,11 @@ hpscd_status solve_batched(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, co
 
 Tuned batched_choice(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, const hpscd_opts* o) {
   auto it = c->tuned.find(batch_key(count, sys));
-  Tuned t = it != c->tuned.end() ? it->second : Tuned{1, batched_rows_per_wave()};
-  if (o->block > 0) t.B = o->block;
+  Tuned t = it != c->tuned.end() ? it->second : Tuned{1, batched_rows_per_wave(1)};
+  if (o->block > 0) t.B = o->block + (t.B & kBatchWide);  // (the tuned shape stays)
+  // team_threads asks for a workgroup shape: 256 (four waves) or 512 (eight)
+  if (o->team_threads == 256) t.B = batched_block(t.B);
+  else if (o->team_threads == 512) t.B = batched_block(t.B) + kBatchWide;
   return t;
 }
 
@@ -882,14 +887,16 @@ hpscd_status hpscd_autotune_batched(hpscd_ctx* ctx, int32_t count, const hpscd_s
     hpscd_status rc = validate_batch(count, sys, Xpool, ypool, opts, apool);
     if (rc != HPSCD_OK) return rc;
     if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
-    // Candidates: the block size B (columns per reduction round) and the
-    // work split (systems small enough for one wave share a workgroup four
-    // ways, or every system gets a whole workgroup).
+    // Candidates: the block size B (columns per reduction round), the
+    // workgroup shape (four waves of eight chunks per thread, or eight of
+    // four), and the work split (systems small enough for one wave share a
+    // workgroup, one per wave, or every system gets a whole workgroup).
     double best = 1e300;
-    Tuned choice{1, batched_rows_per_wave()};
-    for (int B : {1, 2, 4}) {
-      if (!batched_variant_exists(B)) continue;
-      for (int64_t split : {(int64_t)batched_rows_per_wave(), (int64_t)0}) {
+    Tuned choice{1, batched_rows_per_wave(1)};
+    for (int code : {1, 2, 4, 1 + kBatchWide, 2 + kBatchWide, 4 + kBatchWide}) {
+      if (!batched_variant_exists(code)) continue;
+      const int B = code;  // (the variant code travels as the block argument)
+      for (int64_t split : {(int64_t)batched_rows_per_wave(code), (int64_t)0}) {
         double t = 1e300;
         for (int rep = 0; rep < 2; ++rep) {
           hpscd_info inf;

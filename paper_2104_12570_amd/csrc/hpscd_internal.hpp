@@ -43,11 +43,11 @@ struct SysDesc {
 };
 
 // One unit of batched work: a system solved by the whole workgroup, or up to
-// four systems solved by one wave each.
+// eight systems solved by one wave each (as many as the workgroup has waves).
 struct WorkItem {
   int32_t mode;           // 0 = workgroup team, 1 = wave teams
   int32_t count;          // systems in the item
-  int32_t sys[4];
+  int32_t sys[8];
 };
 
 struct BatchArgs {
@@ -83,11 +83,16 @@ int sweep_max_workgroups(int T, int R, int B, bool bf16, bool grid, int D);
 bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid, int D);
 
 hipError_t launch_batched(int B, const BatchArgs& a, int grid, hipStream_t s);
-int batched_threads();
-int batched_rows_per_wave();
-int batched_rows_per_wg();
-int batched_max_blocks_per_cu(int B);
-bool batched_variant_exists(int B);
+int batched_threads(int code);
+// Batched kernel variants are named by a code: the block size (1, 2 or 4),
+// plus kBatchWide for workgroups of eight waves with four chunks per thread
+// instead of four waves with eight (more column chains resident per CU).
+constexpr int kBatchWide = 16;
+inline int batched_block(int code) { return code & (kBatchWide - 1); }
+int batched_rows_per_wave(int code);
+int batched_rows_per_wg(int code);
+int batched_max_blocks_per_cu(int code);
+bool batched_variant_exists(int code);
 
 // Column statistics: rdn = 1/<X_j,X_j> and the in-block Gram, FP64 sums.
 // cross: NULL, or [nb][B*B] receiving <X_{b,l}, X_{b-1,i}> at l*B + i (zero for b = 0).

@@ -2206,11 +2206,16 @@ __global__ void __launch_bounds__(T) k_sweep_pipe(SolveArgs A) {
 // (rows over T threads, reductions through LDS) or up to NW systems solved
 // by one wave each (rows over 64 lanes, reductions by DPP only, no barrier).
 // --------------------------------------------------------------------------
-constexpr int BT = 256;     // threads per batched workgroup
-constexpr int BR = 8;       // FP32 chunks per thread: 8192 rows per workgroup, 2048 per wave
+// Workgroup shapes (both 8192 rows): four waves of eight FP32 chunks per
+// thread (2048 rows per wave team), or eight waves of four (1024 rows per
+// wave team, twice the column chains resident per CU in the same registers).
+template <int W> struct BShape {
+  static constexpr int T = W ? 512 : 256;  // threads per workgroup
+  static constexpr int R = W ? 4 : 8;      // chunks per thread
+};
 
-template <int TT, int R, int B>
-__device__ inline void team_solve(const BatchArgs& A, int sidx, int ttid, float (&red)[2][BT / WAVE][B + 1]) {
+template <int TT, int R, int B, int NWG>
+__device__ inline void team_solve(const BatchArgs& A, int sidx, int ttid, float (&red)[2][NWG][B + 1]) {
   using S = F32;
   using raw = S::raw_t;
   constexpr int VEC = S::VEC;
@@ -2362,8 +2367,9 @@ __device__ inline void team_solve(const BatchArgs& A, int sidx, int ttid, float 
   }
 }
 
-template <int B>
-__global__ void __launch_bounds__(BT) k_batched(BatchArgs A) {
+template <int B, int W>
+__global__ void __launch_bounds__(BShape<W>::T) k_batched(BatchArgs A) {
+  constexpr int BT = BShape<W>::T, BR = BShape<W>::R;
   constexpr int NW = BT / WAVE;
   __shared__ float red[2][NW][B + 1];
   __shared__ int s_item;
@@ -2376,9 +2382,9 @@ __global__ void __launch_bounds__(BT) k_batched(BatchArgs A) {
     if (it >= A.nitems) break;
     const WorkItem w = A.items[it];
     if (w.mode == 0) {
-      team_solve<BT, BR, B>(A, w.sys[0], tid, red);
+      team_solve<BT, BR, B, NW>(A, w.sys[0], tid, red);
     } else if (wave < w.count) {
-      team_solve<WAVE, BR, B>(A, w.sys[wave], tid & (WAVE - 1), red);
+      team_solve<WAVE, BR, B, NW>(A, w.sys[wave], tid & (WAVE - 1), red);
     }
   }
 }
@@ -2493,32 +2499,42 @@ hipError_t launch_sweep(int T, int R, int B, bool bf16, bool grid, int D, const 
   return hipLaunchKernel(v->fn, g, b, kargs, 0, s);
 }
 
-#define HPSCD_BATCHED_VARIANTS(X_) X_(1) X_(2) X_(4)
-struct BVariant { int B; const void* fn; };
-#define HPSCD_BENTRY(B) {B, reinterpret_cast<const void*>(&k_batched<B>)},
+#define HPSCD_BATCHED_VARIANTS(X_) X_(1, 0) X_(2, 0) X_(4, 0) X_(1, 1) X_(2, 1) X_(4, 1)
+struct BVariant { int code; const void* fn; int threads, R; };
+#define HPSCD_BENTRY(B, W) \
+  {B + (W ? kBatchWide : 0), reinterpret_cast<const void*>(&k_batched<B, W>), BShape<W>::T, BShape<W>::R},
 static const BVariant kBVariants[] = {HPSCD_BATCHED_VARIANTS(HPSCD_BENTRY)};
 
-static const BVariant* find_bvariant(int B) {
-  for (const BVariant& v : kBVariants) if (v.B == B) return &v;
+static const BVariant* find_bvariant(int code) {
+  for (const BVariant& v : kBVariants) if (v.code == code) return &v;
   return nullptr;
 }
-bool batched_variant_exists(int B) { return find_bvariant(B) != nullptr; }
-int batched_threads() { return BT; }
-int batched_rows_per_wave() { return WAVE * BR * F32::VEC; }
-int batched_rows_per_wg() { return BT * BR * F32::VEC; }
-int batched_max_blocks_per_cu(int B) {
-  const BVariant* v = find_bvariant(B);
+bool batched_variant_exists(int code) { return find_bvariant(code) != nullptr; }
+int batched_threads(int code) {
+  const BVariant* v = find_bvariant(code);
+  return v ? v->threads : 0;
+}
+int batched_rows_per_wave(int code) {
+  const BVariant* v = find_bvariant(code);
+  return v ? WAVE * v->R * F32::VEC : 0;
+}
+int batched_rows_per_wg(int code) {
+  const BVariant* v = find_bvariant(code);
+  return v ? v->threads * v->R * F32::VEC : 0;
+}
+int batched_max_blocks_per_cu(int code) {
+  const BVariant* v = find_bvariant(code);
   if (!v) return 0;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn, BT, 0) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn, v->threads, 0) != hipSuccess) return 0;
   return nb;
 }
-hipError_t launch_batched(int B, const BatchArgs& a, int grid, hipStream_t s) {
-  const BVariant* v = find_bvariant(B);
+hipError_t launch_batched(int code, const BatchArgs& a, int grid, hipStream_t s) {
+  const BVariant* v = find_bvariant(code);
   if (!v) return hipErrorInvalidValue;
   BatchArgs args = a;
   void* kargs[] = {&args};
-  return hipLaunchKernel(v->fn, dim3((unsigned)grid), dim3(BT), kargs, 0, s);
+  return hipLaunchKernel(v->fn, dim3((unsigned)grid), dim3((unsigned)v->threads), kargs, 0, s);
 }
 
 }  // namespace hpscd

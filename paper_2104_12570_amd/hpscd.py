@@ -304,7 +304,7 @@ class BatchResult:
 
 
 def solve_batched(Xpool, ypool, table, a0pool=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, block=0,
-                  flags=0, a_size=None, want_hist=False, tols=None) -> BatchResult:
+                  flags=0, a_size=None, want_hist=False, tols=None, team_threads=0) -> BatchResult:
     """Solve every system of a packed batch in one persistent launch.
     ``table[i] = (m, n, x_off, ldx, y_off, a_off)``; ``tols[i] > 0`` replaces
     ``tol`` for system i."""
@@ -317,7 +317,7 @@ def solve_batched(Xpool, ypool, table, a0pool=None, *, max_sweeps=100, stop=STOP
     if a_size is None:
         a_size = int((table[:, 5] + table[:, 1]).max())
     a = torch.zeros(a_size, dtype=torch.float32, device=Xpool.device)
-    opts = make_opts(max_sweeps, stop, tol, 0, 0, block, flags)
+    opts = make_opts(max_sweeps, stop, tol, 0, 0, block, flags, team_threads)
     hist = np.full((count, max_sweeps + 1), np.nan) if want_hist else None
     sw = np.zeros(count, np.int32)
     cv = np.zeros(count, np.int32)

@@ -225,16 +225,22 @@ def test_batched_full_size_sampled(lib):
         assert abs(own.sweeps - int(r.sweeps[i])) <= 1, (i, own.sweeps, r.sweeps[i])
 
 
-def test_batched_size_boundaries(lib):
-    """Systems at the edges of the batched kernel's work split: m = 2048 (the
-    largest that one wave holds), 2049 (the smallest given a whole
-    workgroup), 8192 (the largest accepted), tiny m, n = 1 and n close to m."""
+@pytest.mark.parametrize("team_threads,block", [(256, 0), (512, 1), (512, 2), (512, 4)])
+def test_batched_size_boundaries(lib, team_threads, block):
+    """Systems at the edges of the batched kernel's work split in both
+    workgroup shapes: m = 1024 and 2048 (the largest that one wave holds with
+    four and eight chunks per thread), 1025 and 2049, 8192 (the largest
+    accepted), tiny m, n = 1 and n close to m; more small systems than a
+    workgroup has waves, so items of wave teams are full and one is partial."""
     rng = np.random.default_rng(77)
-    sizes = [(2048, 40), (2049, 40), (8192, 100), (8192, 1), (2, 1), (3, 2), (100, 90), (64, 50), (1000, 7)]
+    sizes = [(1024, 40), (1025, 40), (2048, 40), (2049, 40), (8192, 100), (8192, 1), (2, 1), (3, 2), (100, 90),
+             (64, 50), (1000, 7), (500, 30), (300, 12), (700, 64), (900, 5), (256, 255)]
     systems = [gen.make_system(rng, m, n, noise=0.01, pad=np.nan) for m, n in sizes]
     b = gen.pack(systems)
-    say("batched boundaries")
-    r = lib.solve_batched(dev(b.Xpool), dev(b.ypool), b.table, max_sweeps=20, want_hist=True)
+    say("batched boundaries", team_threads, block)
+    r = lib.solve_batched(dev(b.Xpool), dev(b.ypool), b.table, max_sweeps=20, want_hist=True,
+                          team_threads=team_threads, block=block)
+    assert r.info["team_threads"] == team_threads
     a = r.a.cpu().numpy()
     for i, s in enumerate(systems):
         ref = oracle.solve(s.Xt, s.y, s.m, max_sweeps=20)
