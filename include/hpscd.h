@@ -77,8 +77,10 @@ typedef struct {
                            5: grid kernel whose polling waves never wait behind column loads
                            (their rows arrive through LDS); 6, 7: grid kernel with one polling
                            wave and a ring of 2 or 3 column blocks requested as soon as a
-                           buffer frees; 8: grid kernel with 16-column blocks and no column
-                           loads in flight during the exchange; 12, 13: grid kernel with a
+                           buffer frees; 8: 16-column blocks through each block's precomputed
+                           step matrix, no column loads in flight during the exchange (a grid,
+                           or one workgroup without exchange for at most 4096 rows); 12, 13:
+                           grid kernel with a
                            dedicated reduction wave, ring of 2 or 3 */
 } hpscd_opts;
 
