@@ -336,42 +336,71 @@ def test_batch_equals_single():
         np.testing.assert_array_equal(r.a, r1.a)
 
 
+def test_batch_warm_start_pool():
+    """a0pool: each system starts from its own slice of the pool (at its
+    a_off), and the result equals the single solve started from that slice,
+    which in turn continues the zero-start iteration exactly: k sweeps from
+    the iterate after j sweeps equal j + k sweeps from zero (up to rounding
+    of the recomputed starting residual)."""
+    b = gen.batch(seed=4, count=5, m_lo=64, m_hi=300, n_lo=3, n_hi=20)
+    first = oracle.solve_batch(b, max_sweeps=3)
+    a0pool = np.zeros(b.a_size)
+    for i, r in enumerate(first):
+        ao = int(b.table[i, 5])
+        a0pool[ao: ao + len(r.a)] = r.a
+    warm = oracle.solve_batch(b, a0pool=a0pool, max_sweeps=4)
+    for i, r in enumerate(warm):
+        s = b.system(i)
+        full = oracle.solve(s.Xt, s.y, s.m, max_sweeps=7)
+        np.testing.assert_allclose(r.a, full.a, rtol=1e-9, atol=1e-12)
+        ao = int(b.table[i, 5])
+        r1 = oracle.solve(s.Xt, s.y, s.m, a0=a0pool[ao: ao + s.n], max_sweeps=4)
+        np.testing.assert_array_equal(r.a, r1.a)
+
+
 # ------------------------------------------------ planted mistakes
 
-@pytest.mark.parametrize("mutant", ["sign", "index", "transpose", "drop_norm"])
+def _run_pins():
+    """The pins of Algorithm 1 above; returns the names of those that fail."""
+    pins = [
+        lambda: test_dyadic_2x2_closed_form(np.float64),
+        test_single_column_closed_form,
+        test_orthogonal_columns_exact_after_one_sweep,
+        test_diagonal_square_system,
+        test_iterates_equal_gauss_seidel_on_normal_equations,
+        test_step_invariants_section4,
+    ]
+    failed = []
+    for p in pins:
+        try:
+            p()
+        except Exception as exc:  # a wrong oracle may also fail by raising
+            failed.append((getattr(p, "__name__", "dyadic"), type(exc).__name__))
+    return failed
+
+
+def test_pins_pass_on_the_oracle():
+    assert _run_pins() == []
+
+
+@pytest.mark.parametrize("mutant", ["sign", "index", "transpose", "drop_norm", "stale_residual"])
 def test_pins_catch_planted_mistakes(mutant, monkeypatch):
-    """Plant a plausible mistake in the oracle (on the CPU) and check that the
-    closed-form pins reject it."""
+    """Plant a plausible mistake IN the oracle (each line of Algorithm 1's
+    inner loop is a function of the oracle module that is replaced here, on
+    the CPU) and check that the pins above reject it."""
     orig_col = ho._col
-
-    if mutant == "sign":
-        def solve_bad(Xt, y, m, max_sweeps):
-            a = np.zeros(Xt.shape[0]); e = np.asarray(y, float).copy()
-            for _ in range(max_sweeps):
-                for j in range(len(a)):
-                    x = orig_col(Xt, j, m); da = (x @ e) / (x @ x)
-                    e = e + x * da; a[j] += da
-            return a
-    elif mutant == "index":
-        def solve_bad(Xt, y, m, max_sweeps):
-            a = np.zeros(Xt.shape[0]); e = np.asarray(y, float).copy(); n = len(a)
-            for _ in range(max_sweeps):
-                for j in range(n):
-                    x = orig_col(Xt, j, m); da = (x @ e) / (x @ x)
-                    e = e - x * da; a[(j + 1) % n] += da
-            return a
-    elif mutant == "transpose":
-        def solve_bad(Xt, y, m, max_sweeps):
-            return oracle.solve(np.ascontiguousarray(Xt[:, :m].T), y, m, max_sweeps=max_sweeps).a
-    else:
-        def solve_bad(Xt, y, m, max_sweeps):
-            a = np.zeros(Xt.shape[0]); e = np.asarray(y, float).copy()
-            for _ in range(max_sweeps):
-                for j in range(len(a)):
-                    x = orig_col(Xt, j, m); da = x @ e
-                    e = e - x * da; a[j] += da
-            return a
-
-    Xt, y, m = _sys([[1, 1], [0, 1]], [2, 1])
-    bad = solve_bad(Xt, y, m, 3)
-    assert bad.tolist() != [1 + 2.0 ** -2, 1 - 2.0 ** -3]
+    if mutant == "sign":         # e <- e + X_j da
+        monkeypatch.setattr(ho, "_residual_update", lambda e, x, da: e + x * da)
+    elif mutant == "index":      # a_{j+1} <- a_{j+1} + da
+        def coef(a, j, da):
+            a[(j + 1) % len(a)] += da
+        monkeypatch.setattr(ho, "_coef_update", coef)
+    elif mutant == "transpose":  # rows of X taken for its columns
+        def col_t(Xt, j, m):
+            return np.asarray(Xt[:m, j] if Xt.shape[0] >= m else orig_col(Xt, j, m), dtype=np.float64)
+        monkeypatch.setattr(ho, "_col", col_t)
+    elif mutant == "drop_norm":  # da = <X_j, e> without the division
+        monkeypatch.setattr(ho, "_step_size", lambda x, e, d: x @ e)
+    else:                        # the residual never updated
+        monkeypatch.setattr(ho, "_residual_update", lambda e, x, da: e)
+    assert _run_pins(), f"no pin rejects the '{mutant}' mistake"

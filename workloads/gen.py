@@ -31,7 +31,7 @@ __all__ = [
     "System", "Batch", "round_up", "make_system", "tall_small", "tall_large",
     "wide", "square_well_conditioned", "orthogonal_columns", "batch_sizes",
     "batch", "pack", "rbf_params", "rbf_system", "rbf_features",
-    "RBF_NPARAM",
+    "RBF_NPARAM", "column_orders", "correlated_group",
 ]
 
 
@@ -148,6 +148,30 @@ def orthogonal_columns(m: int, n: int, seed: int) -> System:
     y = rng.standard_normal(m)
     return System(np.ascontiguousarray(X.T), y, m, n, None,
                   dict(workload="orthogonal_columns", seed=seed))
+
+
+def column_orders(seed: int, sweeps: int, n: int) -> np.ndarray:
+    """Random column orders: row s is a uniformly random permutation of
+    0..n-1 (the order of sweep s + 1), int32, shape (sweeps, n)."""
+    rng = np.random.default_rng(seed)
+    return np.argsort(rng.random((sweeps, n)), axis=1, kind="stable").astype(np.int32)
+
+
+def correlated_group(m: int, n: int, seed: int, k: int = 3, eps: float = 1e-3,
+                     at: int = 0, dtype=np.float32) -> System:
+    """Gaussian tall system (noise 0.01) whose columns ``at .. at+k-1`` are
+    nearly equal: X_{at+i} = X_at + eps·z_i with z_i iid N(0,1)."""
+    rng = np.random.default_rng(seed)
+    s = make_system(rng, m, n, noise=0.01, dtype=dtype)
+    for i in range(1, k):
+        z = rng.standard_normal(m).astype(dtype)
+        s.Xt[at + i, :m] = s.Xt[at, :m] + dtype(eps) * z
+    y64 = np.zeros(m)
+    for j in range(n):
+        y64 += s.Xt[j, :m].astype(np.float64) * s.a_true[j]
+    s.y = (y64 + 0.01 * rng.standard_normal(m)).astype(dtype)
+    s.meta = dict(workload="correlated_group", seed=seed, k=k, eps=eps, at=at)
+    return s
 
 
 # --------------------------------------------------------------------------
