@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define HPSCD_VERSION 1
+#define HPSCD_VERSION 2
 
 typedef struct hpscd_ctx hpscd_ctx;
 
@@ -53,8 +53,12 @@ typedef enum {
 typedef enum {
   HPSCD_STOP_NONE = 0,       /* run exactly max_sweeps sweeps */
   HPSCD_STOP_REL_CHANGE = 1, /* stop after sweep s >= 1 when hist[s-1] - hist[s] < tol*hist[s] */
-  HPSCD_STOP_REL_RESID = 2   /* stop when ||e|| < tol*||y||: tested before the first sweep, after
+  HPSCD_STOP_REL_RESID = 2,  /* stop when ||e|| < tol*||y||: tested before the first sweep, after
                                 every sweep, and every check_cols column steps if check_cols > 0 */
+  HPSCD_STOP_REL_GRAD = 3    /* stop after sweep s when ||X^T e||_2 < tol*||X^T y||_2 (least-squares
+                                systems, whose residual does not vanish).  X^T e is one more pass
+                                over X after every sweep (FP64 sums of the single-precision e);
+                                single-system FP32 solves only.  A zero residual or gradient stops. */
 } hpscd_stop;
 
 #define HPSCD_F_NO_FINAL_CHECK 1 /* skip the FP64 ||y - X·a|| pass (final_rel_resid = NaN) */
@@ -73,15 +77,23 @@ typedef struct {
   int32_t team_threads; /* threads per workgroup; 0 = library choice.  Batched calls: 256
                            (four waves, eight chunks per thread) or 512 (eight waves, four) */
   int32_t depth;        /* kernel kind; 0 = library choice.  2, 3: prefetch ring of 2 or 3 blocks;
-                           4: pipelined grid kernel, or a 4-block ring for one workgroup;
+                           4: a 4-block ring (one workgroup only);
                            5: grid kernel whose polling waves never wait behind column loads
-                           (their rows arrive through LDS); 6, 7: grid kernel with one polling
-                           wave and a ring of 2 or 3 column blocks requested as soon as a
-                           buffer frees; 8: 16-column blocks through each block's precomputed
-                           step matrix, no column loads in flight during the exchange (a grid,
-                           or one workgroup without exchange for at most 4096 rows); 12, 13:
-                           grid kernel with a
-                           dedicated reduction wave, ring of 2 or 3 */
+                           (their rows arrive through LDS); 8: 16-column blocks through each
+                           block's precomputed step matrix, no column loads in flight during the
+                           exchange (a grid, or one workgroup without exchange for at most 4096
+                           rows) */
+  /* Variants of the method (single-system FP32 solves, kernel kind 8 only; the block size is 16): */
+  int32_t thr;          /* Section 7, Algorithm 2 (HPSCDP): every sweep takes the columns in consecutive
+                           blocks of thr (the last block holds what remains); all columns of a block step
+                           against the residual at the block's start, then e takes the whole block.
+                           0 or 1 = Algorithm 1.  Not combined with `order`. */
+  const int32_t* order; /* Section 2's randomly selected index: NULL = cyclic order, else a DEVICE array
+                           [max_sweeps][n] whose row s-1 lists the columns visited in sweep s (each row a
+                           permutation of 0..n-1, not checked: a repeated or missing index changes the
+                           method, an index outside 0..n-1 is an error the caller must not make).  The
+                           statistics of the sweep's 16-column blocks are recomputed before every sweep
+                           (one more pass over X per sweep); X must be smaller than 4 GiB. */
 } hpscd_opts;
 
 typedef struct {
@@ -90,7 +102,7 @@ typedef struct {
   int64_t cols_done;       /* column steps performed */
   int64_t zero_cols;       /* columns with <X_j, X_j> = 0, skipped (da = 0) */
   double final_norm;       /* ||e||_2 of the running single-precision residual at exit */
-  double final_rel_resid;  /* ||y - X·a||_2 / ||y||_2 recomputed with FP64 sums (NaN if skipped) */
+  double final_rel_resid;  /* ||y - X·a||_2 / ||y||_2 of the returned (FP32) a, FP64 sums (NaN if skipped) */
   double y_norm;           /* ||y||_2 */
   int32_t block_used;      /* B: columns per reduction round */
   int32_t team_wgs;        /* workgroups in the team (1 = one workgroup) */
@@ -99,10 +111,13 @@ typedef struct {
   double sweep_ms;         /* device time of the sweep kernels (HIP events) */
   double total_ms;         /* device time of the whole call (HIP events) */
   int32_t kernel_kind;     /* sweep kernel used (the values of hpscd_opts.depth); 0 for batched calls */
+  int32_t diverged;        /* 1 if ||e|| grew by more than 0.1 % over some sweep (Algorithm 2 with
+                              strongly correlated columns in one block; never for Algorithm 1) */
+  double rel_grad;         /* HPSCD_STOP_REL_GRAD: ||X^T e||/||X^T y|| at the last test; else NaN */
 } hpscd_info;
 
 /* Fill *o with defaults: max_sweeps 100, HPSCD_STOP_NONE, tol 0, no checks,
- * no refresh, block 0, flags 0. */
+ * no refresh, block 0, flags 0, Algorithm 1 (thr 0), cyclic order. */
 void hpscd_default_opts(hpscd_opts* o);
 
 /* Create a context on HIP device `device` (owns the workspace).  Returns
@@ -143,6 +158,25 @@ hpscd_status hpscd_convert_bf16(hpscd_ctx* ctx, int64_t rows, int64_t cols, cons
  * e_out: NULL or m floats.  norm_out: NULL or host double, receives ||r||_2. */
 hpscd_status hpscd_residual_f64(hpscd_ctx* ctx, int64_t m, int64_t n, const float* X, int64_t ldx,
                                 const float* y, const float* a, float* e_out, double* norm_out, void* stream);
+
+/* Feature selection with HPSCD (Section 8, Algorithm 3, HPSCDF).  Starting
+ * from a = a0 (zero if NULL) and e = y - X·a, F times: take the step
+ * da_j = <X_j, e>/<X_j, X_j> of every column against the same e, choose the
+ * column j^ not selected yet whose step leaves the smallest squared error
+ * ||e - X_j da_j||^2 = ||e||^2 - <X_j,e>^2/<X_j,X_j> (the largest
+ * <X_j,e>^2/<X_j,X_j>; ties to the lowest index; zero columns never), then
+ * a_j^ += da_j^ and e -= X_j^ da_j^.  tol > 0 is the section's while-loop
+ * variant: selection stops before a column whose step lowers ||e||^2 by less
+ * than tol*||e||^2.  The residual and the inner products are FP64 (X is read
+ * as FP32); every selection is one pass over X (HBM-bound).
+ * X: m x n column-major FP32 as hpscd_solve_f32.  a0: NULL or n floats.
+ * a_out: n floats (device).  J_out: host, F entries (the selected columns in
+ * order; entries past *selected are -1).  da_out, hist: NULL or host arrays
+ * of F and F+1 doubles (the steps taken; ||e||_2 before the first and after
+ * each selection).  selected: host, receives the number of columns chosen. */
+hpscd_status hpscd_select_f32(hpscd_ctx* ctx, int64_t m, int64_t n, const float* X, int64_t ldx, const float* y,
+                              const float* a0, int32_t F, double tol, float* a_out, int32_t* J_out,
+                              double* da_out, double* hist, int32_t* selected, void* stream);
 
 /* Batched form: `count` independent systems in one persistent launch.
  * sys[i] gives system i's sizes and element offsets into the pools; every
@@ -205,13 +239,21 @@ hpscd_status hpscd_abort(hpscd_ctx* ctx);
  * of Algorithm 1 (the algorithm's first line allows any initial guess).
  * Parameter vector (FP32, device): W1[h1][in], b1[h1], W2[h2][h1], b2[h2],
  * W3[out][h2], b3[out] (row o of a W holds the weights of output unit o).
+ * With an output scaling (below) the output and the loss are taken in
+ * standardised units.
  * x, target, y, flat and grad_flat are device pointers; rows are row-major
  * ([batch][in], [batch][out]).  All work is queued on `stream`; calls that
  * fill loss_out (host) wait for it.
  * ------------------------------------------------------------------------- */
 typedef struct hpscd_mlp hpscd_mlp;
 
-hpscd_status hpscd_mlp_create(int device, int in, int h1, int h2, int out, hpscd_mlp** res);
+/* A network on the context's device, its parameters drawn by the library:
+ * the weights and biases of each layer uniform in [-1/sqrt(fan_in),
+ * 1/sqrt(fan_in)) (fan_in: that layer's input width); parameter k of the
+ * flat vector takes value k of the SplitMix64 stream started at `seed`
+ * (Steele, Lea and Flood 2014), u = top 53 bits / 2^53, w = (2u - 1)·bound.
+ * The Adam state starts at zero. */
+hpscd_status hpscd_mlp_create(hpscd_ctx* ctx, int in, int h1, int h2, int out, uint64_t seed, hpscd_mlp** res);
 void hpscd_mlp_destroy(hpscd_mlp* net);
 int64_t hpscd_mlp_num_params(const hpscd_mlp* net);
 /* Copy parameters in (and reset the Adam state) / out. */
@@ -225,6 +267,18 @@ hpscd_status hpscd_mlp_grads(hpscd_mlp* net, int batch, const float* x, const fl
 /* One Adam step on L for this batch; loss_out (host, NULL ok) gets L before the step. */
 hpscd_status hpscd_mlp_train_step(hpscd_mlp* net, int batch, const float* x, const float* target, float lr,
                                   float* loss_out, void* stream);
+
+/* Output scaling (standardised targets).  hpscd_mlp_fit_output_scaling sets,
+ * for every output k, mu_k and sd_k to the mean and the sample standard
+ * deviation (FP64 sums; sd at least 1e-12, 1 for one row) of column k of
+ * target[count][out] (device).  From then on the network's output is
+ * y = sd ⊙ (W3 h2 + b3) + mu (hpscd_mlp_forward), and the loss of
+ * hpscd_mlp_grads / hpscd_mlp_train_step compares W3 h2 + b3 with the
+ * standardised target (t - mu) / sd.  A new network has mu = 0, sd = 1.
+ * mu_sd: device, 2*out floats [mu..., sd...] (get: written; set: read). */
+hpscd_status hpscd_mlp_fit_output_scaling(hpscd_mlp* net, int count, const float* target, void* stream);
+hpscd_status hpscd_mlp_get_output_scaling(hpscd_mlp* net, float* mu_sd, void* stream);
+hpscd_status hpscd_mlp_set_output_scaling(hpscd_mlp* net, const float* mu_sd, void* stream);
 
 /* Message of the last failure on this host thread ("" if none). */
 const char* hpscd_last_error(void);

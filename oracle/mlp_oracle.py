@@ -25,6 +25,15 @@ Parameter vector, the same flat layout the library uses: W1[h1][in], b1[h1],
 W2[h2][h1], b2[h2], W3[out][h2], b3[out]; row o of a weight matrix holds the
 weights into output unit o.  Inputs x are rows [batch][in].
 
+Output scaling (standardised targets): mu_k and sd_k are the mean and the
+sample standard deviation of output k over the training targets; the
+network is trained on (t - mu)/sd and answers sd * o + mu.
+
+Initial parameters: parameter k of the flat vector is value k of the
+SplitMix64 stream started at the seed (Steele, Lea and Flood, 2014),
+u = top 53 bits / 2^53, w = (2u - 1) * (1 / sqrt(fan_in)) of its layer,
+rounded to FP32.
+
 Gradients are the chain rule written out (backpropagation):
     dL/do  = 2 (o - t) / (batch * n_out)
     dW3 = dO^T h2, db3 = sum_b dO, dH2 = dO W3
@@ -39,7 +48,8 @@ import math
 import numpy as np
 from scipy.special import erf
 
-__all__ = ["num_params", "unpack", "gelu", "gelu_prime", "forward", "loss", "grads", "adam_step"]
+__all__ = ["num_params", "unpack", "gelu", "gelu_prime", "forward", "loss", "grads", "adam_step",
+           "output_scaling", "forward_scaled", "grads_scaled", "splitmix64", "init_params"]
 
 
 def num_params(shape) -> int:
@@ -119,3 +129,52 @@ def adam_step(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     m_hat = m / (1.0 - beta1 ** step)
     v_hat = v / (1.0 - beta2 ** step)
     return p - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
+def output_scaling(T):
+    """(mu, sd): per-column mean and sample standard deviation of T (rows are
+    samples), sd at least 1e-12 and 1 for a single row."""
+    T = np.asarray(T, dtype=np.float64)
+    mu = T.mean(axis=0)
+    sd = T.std(axis=0, ddof=1) if T.shape[0] > 1 else np.ones(T.shape[1])
+    return mu, np.maximum(sd, 1e-12)
+
+
+def forward_scaled(flat, shape, x, mu, sd):
+    """sd * o + mu: the network's answer in target units."""
+    return np.asarray(sd, np.float64) * forward(flat, shape, x) + np.asarray(mu, np.float64)
+
+
+def grads_scaled(flat, shape, x, t, mu, sd):
+    """Gradient and loss of the network trained on standardised targets."""
+    t = (np.asarray(t, np.float64) - np.asarray(mu, np.float64)) / np.asarray(sd, np.float64)
+    return grads(flat, shape, x, t)
+
+
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(seed, k):
+    """Value k (0-based) of the SplitMix64 stream started at ``seed``: state
+    seed + (k+1)·0x9E3779B97F4A7C15, then the finaliser (xor-shift 30,
+    multiply 0xBF58476D1CE4E5B9, xor-shift 27, multiply 0x94D049BB133111EB,
+    xor-shift 31), all modulo 2^64.  k may be an integer array."""
+    k = np.asarray(k, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & _M64) + (k + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def init_params(shape, seed):
+    """Initial flat parameter vector (FP64 values of the FP32 the library stores)."""
+    n_in, h1, h2, n_out = shape
+    out, k0 = [], 0
+    for fan, rows in ((n_in, h1), (h1, h2), (h2, n_out)):
+        cnt = rows * fan + rows
+        u = (splitmix64(seed, np.arange(k0, k0 + cnt)) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+        bound = 1.0 / math.sqrt(fan)
+        out.append(((2.0 * u - 1.0) * bound).astype(np.float32).astype(np.float64))
+        k0 += cnt
+    return np.concatenate(out)

@@ -94,18 +94,24 @@ __global__ void __launch_bounds__(256) k_colgram(const void* X, int64_t ldx, int
 // G[lane/16 + 4*v][lane % 16] in element v (the instruction's result layout,
 // checked on the device); the entries (l, i <= l) go to the partial sums in
 // the layout of k_colgram.
+// With a column order `map`, block position p = b*16 + j holds column
+// map[p] (the blocks of one sweep in that order).  While ctl[CTL_DONE] is set
+// (`done`), the kernel returns at once.
 template <class S>
 __global__ void __launch_bounds__(256) k_colgram16_mfma(const void* X, int64_t ldx, int64_t m, int64_t n,
-                                                        int64_t rows_per, double* partial) {
+                                                        int64_t rows_per, double* partial, const int32_t* map,
+                                                        const int32_t* done) {
   using raw = typename S::raw_t;
   constexpr int VEC = S::VEC, B = 16, NP = B * (B + 1) / 2;
+  if (done && load_flag(done)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, kq = lane >> 4;
   const int64_t nb = (n + B - 1) / B;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per;
   const int64_t r1 = min(m, r0 + rows_per);
   for (int64_t b = (int64_t)blockIdx.y * 4 + wave; b < nb; b += (int64_t)gridDim.y * 4) {
-    const int64_t col = b * B + j;
+    const int64_t pos = b * B + j;
+    const int64_t col = pos < n ? (map ? (int64_t)map[pos] : pos) : n;
     typedef double d4 __attribute__((ext_vector_type(4)));
     d4 acc = {0.0, 0.0, 0.0, 0.0};
     int64_t row = r0;
@@ -151,8 +157,9 @@ __global__ void __launch_bounds__(256) k_colgram16_mfma(const void* X, int64_t l
 template <int B, bool CROSS>
 __global__ void __launch_bounds__(256) k_colgram_reduce(const double* partial, int PR, int64_t n, double* rdn,
                                                         double* gram, double* cross, int32_t* ctl,
-                                                        int64_t* zero_cols) {
+                                                        int64_t* zero_cols, const int32_t* done) {
   constexpr int NP = B * (B + 1) / 2, NG = B * (B - 1) / 2, NX = CROSS ? B * B : 0, NPX = NP + NX;
+  if (done && load_flag(done)) return;
   const int lane = threadIdx.x & 63;
   const int64_t nb = (n + B - 1) / B;
   const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -175,7 +182,7 @@ __global__ void __launch_bounds__(256) k_colgram_reduce(const double* partial, i
     double r = 0.0;
     if (j < n) {
       if (!(s <= DBL_MAX)) store_flag(&ctl[CTL_NONFINITE], 1);
-      else if (s == 0.0) atomicAdd((unsigned long long*)zero_cols, 1ull);
+      else if (s == 0.0) { if (zero_cols) atomicAdd((unsigned long long*)zero_cols, 1ull); }
       else r = 1.0 / s;
     }
     rdn[b * B + l] = r;
@@ -212,8 +219,20 @@ __global__ void __launch_bounds__(256) k_gram16(const double* gram8, const doubl
 // applied to the unit vector e_k; a zero or padding column (reciprocal norm 0)
 // gives a zero row, i.e. da_l = 0 as in the substitution.  One thread per
 // (block, k); M of block b is row-major at minv[(b*16 + l)*16 + k].
+//
+// Algorithm 2 (Section 7, thr > 1): the columns of a sweep form consecutive
+// blocks of thr, and every column of such a block steps against the residual
+// at that block's start.  Within the 16-column block b (columns j0 .. j0+15)
+// column l belongs to the thr-block starting at s_l = floor((j0+l)/thr)*thr.
+// If s_l < j0 the sweep kernel takes its dot against the residual saved at
+// s_l, so da_l = g_l / <X_l,X_l>.  Otherwise the kernel's dot is against the
+// residual at j0, which still lacks the steps of the columns j0 .. s_l - 1 of
+// this block; the substitution removes exactly those:
+//     da_l = (g_l - sum_{i < s_l - j0} <X_l, X_i> da_i) / <X_l, X_l>.
+// thr = 1 is the substitution of Algorithm 1.
 __global__ void __launch_bounds__(256) k_block_inverse16(const double* rdn, const double* gram, int64_t nb,
-                                                         double* minv) {
+                                                         double* minv, int32_t thr, const int32_t* done) {
+  if (done && load_flag(done)) return;
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= nb * 16) return;
   const int64_t b = t / 16;
@@ -221,18 +240,26 @@ __global__ void __launch_bounds__(256) k_block_inverse16(const double* rdn, cons
   double x[16];
 #pragma unroll
   for (int l = 0; l < 16; ++l) {
+    int upto = l;  // Algorithm 1: every earlier column of the block
+    if (thr > 1) {
+      const int64_t j0 = b * 16;
+      const int64_t s_l = (j0 + l) / thr * thr;
+      upto = s_l < j0 ? 0 : (int)(s_l - j0);
+    }
     double acc = (l == k) ? 1.0 : 0.0;
 #pragma unroll
-    for (int i = 0; i < l; ++i) acc -= gram[b * 120 + l * (l - 1) / 2 + i] * x[i];
+    for (int i = 0; i < l; ++i)
+      if (i < upto) acc -= gram[b * 120 + l * (l - 1) / 2 + i] * x[i];
     x[l] = acc * rdn[b * 16 + l];
     minv[(b * 16 + l) * 16 + k] = x[l];
   }
 }
 
-static hipError_t block_inverse16(const double* rdn, const double* gram, int64_t n, double* minv, hipStream_t s) {
+static hipError_t block_inverse16(const double* rdn, const double* gram, int64_t n, double* minv, hipStream_t s,
+                                  int32_t thr = 0, const int32_t* done = nullptr) {
   const int64_t nb = (n + 15) / 16;
   hipLaunchKernelGGL(k_block_inverse16, dim3((unsigned)((nb * 16 + 255) / 256)), dim3(256), 0, s, rdn, gram, nb,
-                     minv);
+                     minv, thr, done);
   return hipGetLastError();
 }
 
@@ -260,7 +287,7 @@ static hipError_t colgram_impl(const void* X, int64_t ldx, int64_t m, int64_t n,
   if (err != hipSuccess) return err;
   const int64_t total = nb * NPX;
   hipLaunchKernelGGL((k_colgram_reduce<B, CROSS>), dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, partial,
-                     (int)PR, n, rdn, gram, cross, ctl, zero_cols);
+                     (int)PR, n, rdn, gram, cross, ctl, zero_cols, nullptr);
   return hipGetLastError();
 }
 
@@ -269,7 +296,7 @@ static hipError_t colgram_impl(const void* X, int64_t ldx, int64_t m, int64_t n,
 template <class S>
 static hipError_t colgram16_mfma(const void* X, int64_t ldx, int64_t m, int64_t n, double* rdn, double* gram,
                                  double* partial, int64_t partial_cap, int32_t* ctl, int64_t* zero_cols,
-                                 hipStream_t s) {
+                                 hipStream_t s, const int32_t* map, const int32_t* done) {
   constexpr int B = 16, NPX = B * (B + 1) / 2;
   const int64_t nb = (n + B - 1) / B;
   int64_t PR = 1;
@@ -283,18 +310,19 @@ static hipError_t colgram16_mfma(const void* X, int64_t ldx, int64_t m, int64_t 
   PR = (m + rows_per - 1) / rows_per;
   const int64_t NBG = std::min<int64_t>((nb + 3) / 4, 65535);
   hipLaunchKernelGGL((k_colgram16_mfma<S>), dim3((unsigned)PR, (unsigned)NBG), dim3(256), 0, s, X, ldx, m, n,
-                     rows_per, partial);
+                     rows_per, partial, map, done);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int64_t total = nb * NPX;
   hipLaunchKernelGGL((k_colgram_reduce<B, false>), dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, partial,
-                     (int)PR, n, rdn, gram, nullptr, ctl, zero_cols);
+                     (int)PR, n, rdn, gram, nullptr, ctl, zero_cols, done);
   return hipGetLastError();
 }
 
 hipError_t launch_colgram(const void* X, bool bf16, int64_t ldx, int64_t m, int64_t n, int B, double* rdn,
                           double* gram, double* cross, double* partial, int64_t partial_cap, int32_t* ctl,
-                          int64_t* zero_cols, hipStream_t s) {
+                          int64_t* zero_cols, hipStream_t s, const int32_t* map, int32_t thr) {
+  if ((map || thr > 1) && (B != 16 || bf16)) return hipErrorInvalidValue;
 #define HPSCD_CG(BB)                                                                                           \
   case BB:                                                                                                     \
     if (cross)                                                                                                 \
@@ -316,8 +344,10 @@ hipError_t launch_colgram(const void* X, bool bf16, int64_t ldx, int64_t m, int6
       // step matrices into cross.
       if (cross == nullptr) return hipErrorInvalidValue;
       if (!bf16) {
-        hipError_t err = colgram16_mfma<F32>(X, ldx, m, n, rdn, gram, partial, partial_cap, ctl, zero_cols, s);
-        return err != hipSuccess ? err : block_inverse16(rdn, gram, n, cross, s);
+        const int32_t* done = map ? &ctl[CTL_DONE] : nullptr;
+        hipError_t err =
+            colgram16_mfma<F32>(X, ldx, m, n, rdn, gram, partial, partial_cap, ctl, zero_cols, s, map, done);
+        return err != hipSuccess ? err : block_inverse16(rdn, gram, n, cross, s, thr, done);
       }
       const int64_t nb8 = (n + 7) / 8, nb16 = (n + 15) / 16;
       double* cross8 = cross;
@@ -419,7 +449,8 @@ hipError_t launch_colgram_batched(const float* Xpool, const SysDesc* sys, int32_
 // Tall layout: one thread per chunk of 4 rows, looping over the columns.
 __global__ void __launch_bounds__(256) k_resid_rows(const float* X, int64_t ldx, int64_t m, int64_t ncols,
                                                     const float* y, const double* a64, const float* a32,
-                                                    float* e_out, double* partial, const int32_t* skip_if) {
+                                                    float* e_out, double* partial, const int32_t* skip_if,
+                                                    double* e64_out) {
   if (skip_if && *skip_if) return;
   const int64_t row = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -458,6 +489,7 @@ __global__ void __launch_bounds__(256) k_resid_rows(const float* X, int64_t ldx,
     if (i < lim) {
       sq = fma(acc[i], acc[i], sq);
       if (e_out) e_out[row + i] = (float)acc[i];
+      if (e64_out) e64_out[row + i] = acc[i];
     }
   }
   __shared__ double wsum[4];
@@ -510,7 +542,7 @@ __global__ void __launch_bounds__(256) k_resid_cols(const float* X, int64_t ldx,
 
 __global__ void k_resid_cols_reduce(const double* partial, int G, int64_t tile, int64_t row0, int64_t m,
                                     const float* y, float* e_out, double* sq_partial,
-                                    const int32_t* skip_if) {
+                                    const int32_t* skip_if, double* e64_out) {
   if (skip_if && *skip_if) return;
   const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double v = 0.0;
@@ -519,6 +551,7 @@ __global__ void k_resid_cols_reduce(const double* partial, int G, int64_t tile, 
     for (int g = 0; g < G; ++g) s += partial[(int64_t)g * tile + r];
     v = (double)y[row0 + r] - s;
     if (e_out) e_out[row0 + r] = (float)v;
+    if (e64_out) e64_out[row0 + r] = v;
   }
   __shared__ double wsum[4];
   double sq = wave_sum(v * v);
@@ -545,12 +578,12 @@ __global__ void __launch_bounds__(256) k_sum_f64(const double* v, int64_t count,
 
 hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t ncols, const float* y,
                            const double* a64, const float* a32, float* e_out, double* norm2, double* partial,
-                           int64_t partial_cap, const int32_t* skip_if, hipStream_t s) {
+                           int64_t partial_cap, const int32_t* skip_if, hipStream_t s, double* e64_out) {
   if (ncols == 0 || m >= 65536) {
     const int64_t G = (m + 1023) / 1024;
     if (G > partial_cap) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_resid_rows, dim3((unsigned)G), dim3(256), 0, s, X, ldx, m, ncols, y, a64, a32, e_out,
-                       partial, skip_if);
+                       partial, skip_if, e64_out);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     if (norm2) hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, s, partial, G, norm2, 0, skip_if);
@@ -570,7 +603,7 @@ hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t ncols
     hipLaunchKernelGGL(k_resid_cols, dim3((unsigned)G), dim3(256), 0, s, X, ldx, m, t * tile, ncols, cols_per,
                        a64, a32, partial, tile, skip_if);
     hipLaunchKernelGGL(k_resid_cols_reduce, dim3((unsigned)sqn), dim3(256), 0, s, partial, (int)G, tile,
-                       t * tile, m, y, e_out, sqp + t * sqn, skip_if);
+                       t * tile, m, y, e_out, sqp + t * sqn, skip_if, e64_out);
   }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;

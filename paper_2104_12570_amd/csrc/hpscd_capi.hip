@@ -4,6 +4,7 @@
 #include "hpscd_internal.hpp"
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdlib>
 #include <cstdarg>
@@ -95,6 +96,7 @@ struct hpscd_ctx {
   int device = 0;
   int cus = 0;
   DevBuf ctlb, e0, eo, a64, rdn, gram, cross, partial, slots, hist;
+  DevBuf selw;  // feature selection: FP64 residual, inner products, flags, results
   BatchWork bw;
   void* host = nullptr;
   size_t host_cap = 0;
@@ -123,19 +125,32 @@ hpscd_status ensure(DevBuf& b, size_t bytes, const char* what) {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+}  // namespace
+
+int hpscd::ctx_device(const hpscd_ctx* c) { return c->device; }
+
+namespace {
+
 hpscd_status validate_opts(const hpscd_opts* o) {
   if (!o) return fail(HPSCD_EINVAL, "opts is NULL");
   if (o->max_sweeps < 0) return fail(HPSCD_EINVAL, "max_sweeps must be >= 0 (got %d)", o->max_sweeps);
-  if (o->stop < HPSCD_STOP_NONE || o->stop > HPSCD_STOP_REL_RESID)
+  if (o->stop < HPSCD_STOP_NONE || o->stop > HPSCD_STOP_REL_GRAD)
     return fail(HPSCD_EINVAL, "unknown stop rule %d", o->stop);
+  if (o->thr < 0) return fail(HPSCD_EINVAL, "thr must be >= 0 (got %d)", o->thr);
+  if (o->thr > 1 && o->order) return fail(HPSCD_EINVAL, "thr > 1 (Algorithm 2) and a column order are exclusive");
+  if ((o->thr > 1 || o->order) && o->depth != 0 && o->depth != 8)
+    return fail(HPSCD_EINVAL, "Algorithm 2 and column orders run on the wide-block kernel (depth 8) only");
+  if ((o->thr > 1 || o->order) && o->block != 0 && o->block != 16)
+    return fail(HPSCD_EINVAL, "Algorithm 2 and column orders use blocks of 16 columns");
+  if ((o->thr > 1 || o->order) && o->refresh_cols > 0)
+    return fail(HPSCD_EINVAL, "Algorithm 2 and column orders are single-precision solves without refreshes");
   if (!std::isfinite(o->tol) || o->tol < 0.0) return fail(HPSCD_EINVAL, "tol must be finite and >= 0");
   if (o->check_cols < 0) return fail(HPSCD_EINVAL, "check_cols must be >= 0");
   if (o->refresh_cols < 0) return fail(HPSCD_EINVAL, "refresh_cols must be >= 0");
   if (o->block != 0 && o->block != 1 && o->block != 2 && o->block != 4 && o->block != 8 && o->block != 16)
     return fail(HPSCD_EINVAL, "block must be 0, 1, 2, 4, 8 or 16 (got %d)", o->block);
-  if (o->depth != 0 && o->depth != 2 && o->depth != 3 && o->depth != 4 && o->depth != 5 && o->depth != 6 &&
-      o->depth != 7 && o->depth != 8 && o->depth != 12 && o->depth != 13)
-    return fail(HPSCD_EINVAL, "depth (kernel kind) must be 0, 2, 3, 4, 5, 6, 7, 8, 12 or 13 (got %d)", o->depth);
+  if (o->depth != 0 && o->depth != 2 && o->depth != 3 && o->depth != 4 && o->depth != 5 && o->depth != 8)
+    return fail(HPSCD_EINVAL, "depth (kernel kind) must be 0, 2, 3, 4, 5 or 8 (got %d)", o->depth);
   if (o->block == 16 && o->depth != 0 && o->depth != 8)
     return fail(HPSCD_EINVAL, "block 16 runs only on the wide-block grid kernel (depth 8)");
   if ((o->flags & HPSCD_F_FORCE_GRID) && (o->flags & HPSCD_F_FORCE_WG))
@@ -159,12 +174,14 @@ struct Plan {
   bool grid;
   int T, R, B, P, D;
   int rpw;  // rows per workgroup
+  int V;    // method variant of the wide-block kernel
 };
 
 // One planning attempt; `wide` selects the wide-block kernel (16 columns per
 // reduction).
 static hpscd_status plan_try(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hpscd_opts* o, bool wide,
                              Plan* pl) {
+  const int V = o->order ? 2 : (o->thr > 1 ? 1 : 0);
   const int VEC = bf16 ? 8 : 4;
   bool grid;
   if (o->flags & HPSCD_F_FORCE_GRID) grid = true;
@@ -200,19 +217,17 @@ static hpscd_status plan_try(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, cons
     for (int R : {1, 2, 4}) keep.push_back({o->team_threads, R});
     shapes = keep;
   }
-  // Kernel kinds in order of preference (see launch_sweep).  The pipelined
-  // kind (4) tests the stop rule only at sweep ends, so it is only used when
-  // asked for and the caller does not need checks inside a sweep.
+  // Kernel kinds in order of preference (see launch_sweep).
   std::vector<int> kinds;
-  if (grid && o->depth == 4 && o->check_cols > 0 && o->stop == HPSCD_STOP_REL_RESID)
-    return fail(HPSCD_EINVAL, "the pipelined kernel (depth 4) tests the stop rule only at sweep ends");
+  if (grid && o->depth == 4)
+    return fail(HPSCD_EINVAL, "depth 4 (a ring of four blocks) exists for one workgroup only");
   if (o->depth != 0) kinds = {o->depth};
   else if (wide) kinds = {8};
-  else if (grid) kinds = {5, 2, 3};  // 4, 6, 7, 12, 13 are selectable
+  else if (grid) kinds = {5, 2, 3};
   else kinds = {4, 3, 2};         // one workgroup: the deepest ring hides the most load latency
   auto kind_of = [&](int T, int R, int b) {
     for (int k : kinds)
-      if (sweep_variant_exists(T, R, b, bf16, grid, k)) return k;
+      if (sweep_variant_exists(T, R, b, bf16, grid, k, k == 8 ? V : 0)) return k;
     return 0;
   };
   for (auto [T, R] : shapes) {
@@ -226,9 +241,9 @@ static hpscd_status plan_try(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, cons
     int64_t P = grid ? (m + rows - 1) / rows : 1;
     int64_t rpw = rows;
     if (grid) {
-      const int maxw = sweep_max_workgroups(T, R, b, bf16, true, kind);
+      const int maxw = sweep_max_workgroups(T, R, b, bf16, true, kind, V);
       if (P > maxw) continue;
-      const int per_cu = sweep_max_blocks_per_cu(T, R, b, bf16, true, kind);
+      const int per_cu = sweep_max_blocks_per_cu(T, R, b, bf16, true, kind, V);
       if (per_cu <= 0 || P > (int64_t)per_cu * c->cus) continue;
       if (kind == 8 && 4 * P >= 3 * (int64_t)c->cus) {
         // a grid that already covers most CUs spreads its rows over one
@@ -243,7 +258,7 @@ static hpscd_status plan_try(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, cons
         }
       }
     }
-    *pl = Plan{grid, T, R, b, (int)P, kind, (int)rpw};
+    *pl = Plan{grid, T, R, b, (int)P, kind, (int)rpw, V};
     return HPSCD_OK;
   }
   return fail(HPSCD_EINVAL, "no kernel variant fits m=%lld (%s team, block %d)", (long long)m,
@@ -256,7 +271,8 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
   // of the exchange's memory operations queued behind column loads), unless
   // the block cannot be 16 (column checks, refreshes) or the grid would
   // exceed 256 workgroups.
-  if (o->depth == 8 || (o->depth == 0 && o->block == 16)) return plan_try(c, m, n, bf16, o, true, pl);
+  if (o->depth == 8 || (o->depth == 0 && o->block == 16) || o->thr > 1 || o->order)
+    return plan_try(c, m, n, bf16, o, true, pl);
   if (o->depth == 0 && o->block == 0 && o->team_threads == 0 && !bf16) {
     Plan wp;
     if (plan_try(c, m, n, bf16, o, true, &wp) == HPSCD_OK && wp.grid) {
@@ -275,7 +291,7 @@ hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hp
 // system and on 64k..500k-row systems).
 uint32_t poll_delay_ticks(const Plan& pl) {
   if (!pl.grid) return 0;
-  if (pl.D == 5 || pl.D == 6 || pl.D == 7) return (uint32_t)std::min(240.0, 80.0 + 0.6 * pl.P);
+  if (pl.D == 5) return (uint32_t)std::min(240.0, 80.0 + 0.6 * pl.P);
   if (pl.D == 8) return (uint32_t)std::min(200.0, 65.0 + 0.22 * pl.P);
   if (pl.D == 2 || pl.D == 3) return (uint32_t)std::min(160.0, 0.65 * pl.P);
   return 0;
@@ -301,54 +317,105 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
-hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, int64_t ldxs, bool bf16,
-                          const float* X32, int64_t ldx32, const float* y, const float* a0, const hpscd_opts* o,
-                          float* a_out, double* hist, hpscd_info* info, hipStream_t st) {
-  Plan pl;
-  hpscd_status rc = plan_single(c, m, n, bf16, o, &pl);
-  if (rc != HPSCD_OK) return rc;
-  HIP_TRY(hipSetDevice(c->device));
+// Device workspace of one single-system solve: the context's grow-only
+// buffers, or regions of a fixed scratch area.
+struct Work {
+  CtlBlock* cb;
+  float *e0, *eo;
+  double *a64, *rdn, *gram, *cross, *partial, *hist;
+  uint64_t* slots;
+  int64_t partial_cap;
+};
+
+// Sizes (bytes) of the workspace regions of a solve planned as `pl`.
+struct WorkSizes {
+  size_t ctl, e0, eo, a64, rdn, gram, cross, partial, slots, hist;
+  int64_t partial_cap;
+  size_t total() const { return ctl + e0 + eo + a64 + rdn + gram + cross + partial + slots + hist; }
+};
+
+WorkSizes work_sizes(const Plan& pl, int64_t m, int64_t n, const hpscd_opts* o) {
   const int B = pl.B;
   const int64_t nb = (n + B - 1) / B;
   const int NG = B * (B - 1) / 2;
-  const int64_t hist_len = (int64_t)o->max_sweeps + 1;
-  const int64_t partial_cap = std::max<int64_t>({(int64_t)1 << 21, nb * B * 80, (m + 1023) / 1024 + 8});
+  auto r256 = [](size_t b) { return (b + 255) / 256 * 256; };
+  WorkSizes w{};
+  // partial sums of the column statistics (rows split ~8192 ways over the
+  // blocks, at most), of the residual passes, and of X^T e (gradient rule)
+  int64_t cap = std::max<int64_t>({(int64_t)1 << 21, nb * B * 80, (m + 1023) / 1024 + 8});
+  if (o->stop == HPSCD_STOP_REL_GRAD) cap = std::max<int64_t>(cap, plan_xtv(m, n, (int64_t)1 << 22).need);
+  w.partial_cap = cap;
+  w.ctl = r256(sizeof(CtlBlock));
+  w.e0 = r256((size_t)m * 4);
+  w.eo = r256((size_t)m * 4);
+  w.a64 = r256((size_t)n * 8);
+  w.rdn = r256((size_t)nb * B * 8);
+  w.gram = r256((size_t)std::max<int64_t>(1, nb * NG) * 8);
+  w.cross = r256((size_t)nb * B * B * 8);
+  w.partial = r256((size_t)cap * 8);
+  w.slots = r256((size_t)4 * (B + 1) * std::max(1, pl.P) * 8);
+  w.hist = r256((size_t)((int64_t)o->max_sweeps + 1) * 8);
+  return w;
+}
 
-  if ((rc = ensure(c->ctlb, sizeof(CtlBlock), "ctl")) ||
-      (rc = ensure(c->e0, (size_t)m * 4, "e0")) || (rc = ensure(c->eo, (size_t)m * 4, "e")) ||
-      (rc = ensure(c->a64, (size_t)n * 8, "a64")) || (rc = ensure(c->rdn, (size_t)nb * B * 8, "rdn")) ||
-      (rc = ensure(c->gram, (size_t)std::max<int64_t>(1, nb * NG) * 8, "gram")) ||
-      (rc = ensure(c->cross, (size_t)nb * B * B * 8, "cross")) ||
-      (rc = ensure(c->partial, (size_t)partial_cap * 8, "partial")) ||
-      (rc = ensure(c->slots, (size_t)4 * (B + 1) * std::max(1, pl.P) * 8, "slots")) ||
-      (rc = ensure(c->hist, (size_t)hist_len * 8, "hist")))
+hpscd_status work_from_ctx(hpscd_ctx* c, const WorkSizes& z, Work* w) {
+  hpscd_status rc;
+  if ((rc = ensure(c->ctlb, z.ctl, "ctl")) || (rc = ensure(c->e0, z.e0, "e0")) || (rc = ensure(c->eo, z.eo, "e")) ||
+      (rc = ensure(c->a64, z.a64, "a64")) || (rc = ensure(c->rdn, z.rdn, "rdn")) ||
+      (rc = ensure(c->gram, z.gram, "gram")) || (rc = ensure(c->cross, z.cross, "cross")) ||
+      (rc = ensure(c->partial, z.partial, "partial")) || (rc = ensure(c->slots, z.slots, "slots")) ||
+      (rc = ensure(c->hist, z.hist, "hist")))
     return rc;
-  if ((rc = c->host_ensure(sizeof(CtlBlock) + (size_t)hist_len * 8))) return rc;
+  *w = Work{c->ctlb.as<CtlBlock>(), c->e0.as<float>(), c->eo.as<float>(), c->a64.as<double>(),
+            c->rdn.as<double>(), c->gram.as<double>(), c->cross.as<double>(), c->partial.as<double>(),
+            c->hist.as<double>(), c->slots.as<uint64_t>(), (int64_t)(c->partial.cap / 8)};
+  return HPSCD_OK;
+}
 
-  CtlBlock* cb = c->ctlb.as<CtlBlock>();
+// Host-side landing area of a solve's results: the control block and hist.
+struct HostOut {
+  CtlBlock* cb;
+  double* hist;  // max_sweeps + 1 doubles
+};
+
+hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, int64_t ldxs, bool bf16,
+                          const float* X32, int64_t ldx32, const float* y, const float* a0, const hpscd_opts* o,
+                          float* a_out, double* hist, hpscd_info* info, hipStream_t st, const Plan& pl,
+                          const Work& w, const HostOut& ho) {
+  HIP_TRY(hipSetDevice(c->device));
+  const int B = pl.B;
+  const int64_t nb = (n + B - 1) / B;
+  const int64_t hist_len = (int64_t)o->max_sweeps + 1;
+  const int64_t partial_cap = w.partial_cap;
+  const bool grad_rule = o->stop == HPSCD_STOP_REL_GRAD;
+  const bool ordered = pl.V == 2;
+
+  CtlBlock* cb = w.cb;
   int32_t* ctl = reinterpret_cast<int32_t*>(cb);
   int64_t* ctl64 = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(cb) + offsetof(CtlBlock, ctl64));
   double* fstat = reinterpret_cast<double*>(reinterpret_cast<char*>(cb) + offsetof(CtlBlock, fstat));
   double* ynorm2 = reinterpret_cast<double*>(reinterpret_cast<char*>(cb) + offsetof(CtlBlock, ynorm2));
   double* fnorm2 = reinterpret_cast<double*>(reinterpret_cast<char*>(cb) + offsetof(CtlBlock, fnorm2));
-  double* partial = c->partial.as<double>();
+  double* partial = w.partial;
 
   HIP_TRY(hipEventRecord(c->ev[0], st));
   HIP_TRY(launch_fill_i32(ctl, sizeof(CtlBlock) / 4, 0, st));
-  HIP_TRY(launch_fill_f64(c->hist.as<double>(), hist_len, std::numeric_limits<double>::quiet_NaN(), st));
-  if (pl.grid) HIP_TRY(launch_fill_u64(c->slots.as<uint64_t>(), 4 * (int64_t)(B + 1) * pl.P, 0, st));
-  HIP_TRY(launch_a_init(c->a64.as<double>(), a0, n, st));
+  HIP_TRY(launch_fill_f64(w.hist, hist_len, std::numeric_limits<double>::quiet_NaN(), st));
+  if (pl.grid) HIP_TRY(launch_fill_u64(w.slots, 4 * (int64_t)(B + 1) * pl.P, 0, st));
+  HIP_TRY(launch_a_init(w.a64, a0, n, st));
   HIP_TRY(launch_residual(X32, ldx32, m, 0, y, nullptr, nullptr, nullptr, ynorm2, partial, partial_cap, nullptr, st));
   const float* e0 = y;
   if (a0) {
-    HIP_TRY(launch_residual(X32, ldx32, m, n, y, nullptr, a0, c->e0.as<float>(), nullptr, partial, partial_cap,
-                            nullptr, st));
-    e0 = c->e0.as<float>();
+    HIP_TRY(launch_residual(X32, ldx32, m, n, y, nullptr, a0, w.e0, nullptr, partial, partial_cap, nullptr, st));
+    e0 = w.e0;
   }
-  const bool pipelined = pl.grid && pl.D == 4;  // (one workgroup: D = 4 is a 4-block ring)
-  HIP_TRY(launch_colgram(Xs, bf16, ldxs, m, n, B, c->rdn.as<double>(), c->gram.as<double>(),
-                         (pipelined || B == 16) ? c->cross.as<double>() : nullptr, partial, partial_cap,
-                         ctl, &ctl64[C64_ZERO_COLS], st));
+  // column statistics (under a column order: before every sweep, below)
+  if (!ordered)
+    HIP_TRY(launch_colgram(Xs, bf16, ldxs, m, n, B, w.rdn, w.gram, B == 16 ? w.cross : nullptr, partial, partial_cap,
+                           ctl, &ctl64[C64_ZERO_COLS], st, nullptr, pl.V == 1 ? o->thr : 0));
+  if (grad_rule)
+    HIP_TRY(launch_grad_stop(X32, ldx32, m, n, y, true, 0, o->tol, partial, partial_cap, ctl, ctl64, fstat, w.hist,
+                             st));
   HIP_TRY(hipEventRecord(c->ev[1], st));
 
   SolveArgs A{};
@@ -356,14 +423,13 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   A.ldx = ldxs;
   A.m = m;
   A.n = n;
-  A.rdn = c->rdn.as<double>();
-  A.gram = c->gram.as<double>();
-  A.cross = c->cross.as<double>();
-  A.minv = B == 16 ? c->cross.as<double>() : nullptr;
-  A.a64 = c->a64.as<double>();
-  A.e_out = c->eo.as<float>();
-  A.hist = c->hist.as<double>();
-  A.slots = c->slots.as<uint64_t>();
+  A.rdn = w.rdn;
+  A.gram = w.gram;
+  A.minv = B == 16 ? w.cross : nullptr;
+  A.a64 = w.a64;
+  A.e_out = w.eo;
+  A.hist = w.hist;
+  A.slots = w.slots;
   A.ctl = ctl;
   A.fstat = fstat;
   A.ctl64 = ctl64;
@@ -376,8 +442,13 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   A.rows_per_wg = pl.rpw;
   A.timeout_ticks = kTimeoutTicks;
   A.poll_delay = poll_delay_ticks(pl);
+  A.thr = o->thr;
+  A.order = o->order;
   const int64_t total = (int64_t)o->max_sweeps * nb + 1;
-  const int64_t seg = (o->refresh_cols > 0) ? std::max<int64_t>(1, o->refresh_cols / B) : total;
+  // launch segments: a refresh period, or one sweep when something runs
+  // between sweeps (the gradient rule's pass, a column order's statistics)
+  const int64_t seg = (grad_rule || ordered) ? nb
+                      : (o->refresh_cols > 0) ? std::max<int64_t>(1, o->refresh_cols / B) : total;
   const bool coop = pl.grid && !(o->flags & HPSCD_F_NO_COOP);
   int refreshes = 0;
   // bf16 form with the relative-residual rule: the running residual comes
@@ -385,13 +456,26 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   // residual recomputed from X32 (FP64 sums); if that one is not yet under
   // the tolerance, the sweeps resume where they stopped.
   const bool confirm = bf16 && o->refresh_cols > 0 && o->stop == HPSCD_STOP_REL_RESID;
-  CtlBlock* hcb = reinterpret_cast<CtlBlock*>(c->host);
+  CtlBlock* hcb = ho.cb;
   bool resumed = false;
   for (int64_t kb = 0; kb < total;) {
-    A.e0 = (kb == 0 && !resumed) ? e0 : c->eo.as<float>();
+    A.e0 = (kb == 0 && !resumed) ? e0 : w.eo;
     A.blk_begin = kb;
     A.blk_end = std::min(total, (kb / seg + 1) * seg);  // refreshes stay on multiples of refresh_cols
-    HIP_TRY(launch_sweep(pl.T, pl.R, B, bf16, pl.grid, pl.D, A, st, coop));
+    const int64_t sweep = kb / nb;                       // (segments of one sweep: the sweep it runs)
+    if (ordered && sweep < o->max_sweeps)
+      HIP_TRY(launch_colgram(Xs, false, ldxs, m, n, B, w.rdn, w.gram, w.cross, partial, partial_cap, ctl,
+                             sweep == 0 ? &ctl64[C64_ZERO_COLS] : nullptr, st, o->order + sweep * n, 0));
+    HIP_TRY(launch_sweep(pl.T, pl.R, B, bf16, pl.grid, pl.D, A, st, coop, pl.V));
+    if (grad_rule && A.blk_end < total)
+      HIP_TRY(launch_grad_stop(X32, ldx32, m, n, w.eo, false, (int32_t)(sweep + 1), o->tol, partial, partial_cap, ctl,
+                               ctl64, fstat, w.hist, st));
+    if ((grad_rule || ordered) && A.blk_end < total) {
+      // stop queueing sweeps once the solve has ended
+      HIP_TRY(hipMemcpyAsync(hcb, cb, sizeof(CtlBlock), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (hcb->ctl[CTL_DONE]) break;
+    }
     if (confirm) {
       HIP_TRY(hipMemcpyAsync(hcb, cb, sizeof(CtlBlock), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
@@ -399,8 +483,8 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
         if (!hcb->ctl[CTL_CONVERGED] || hcb->ctl[CTL_ERR] || hcb->ctl[CTL_NONFINITE]) break;
         const int64_t cs = hcb->ctl64[C64_COLS];
         const int64_t touched = a0 ? n : std::min(n, cs);
-        HIP_TRY(launch_residual(X32, ldx32, m, touched, y, c->a64.as<double>(), nullptr, c->eo.as<float>(), fnorm2,
-                                partial, partial_cap, nullptr, st));
+        HIP_TRY(launch_residual(X32, ldx32, m, touched, y, w.a64, nullptr, w.eo, fnorm2, partial, partial_cap, nullptr,
+                                st));
         ++refreshes;
         HIP_TRY(hipMemcpyAsync(hcb, cb, sizeof(CtlBlock), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
@@ -409,7 +493,7 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
         // not yet: clear the stop and resume at the block where it fired
         HIP_TRY(launch_fill_i32(&ctl[CTL_CONVERGED], 1, 0, st));
         HIP_TRY(launch_fill_i32(&ctl[CTL_DONE], 1, 0, st));
-        if (pl.grid) HIP_TRY(launch_fill_u64(c->slots.as<uint64_t>(), 4 * (int64_t)(B + 1) * pl.P, 0, st));
+        if (pl.grid) HIP_TRY(launch_fill_u64(w.slots, 4 * (int64_t)(B + 1) * pl.P, 0, st));
         kb = (cs / n) * nb + (cs % n) / B;
         resumed = true;
         continue;
@@ -418,26 +502,26 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
     if (o->refresh_cols > 0 && A.blk_end < total) {
       const int64_t cols = (A.blk_end / nb) * n + (A.blk_end % nb) * B;
       const int64_t touched = a0 ? n : std::min(n, cols);
-      HIP_TRY(launch_residual(X32, ldx32, m, touched, y, c->a64.as<double>(), nullptr, c->eo.as<float>(), nullptr,
-                              partial, partial_cap, &ctl[CTL_DONE], st));
+      HIP_TRY(launch_residual(X32, ldx32, m, touched, y, w.a64, nullptr, w.eo, nullptr, partial, partial_cap,
+                              &ctl[CTL_DONE], st));
       ++refreshes;
     }
     kb = A.blk_end;
   }
   HIP_TRY(hipEventRecord(c->ev[2], st));
-  HIP_TRY(launch_a_out(c->a64.as<double>(), a_out, n, st));
+  HIP_TRY(launch_a_out(w.a64, a_out, n, st));
+  // the final check judges the coefficients returned (single precision)
   const bool check = !(o->flags & HPSCD_F_NO_FINAL_CHECK);
   if (check)
-    HIP_TRY(launch_residual(X32, ldx32, m, n, y, c->a64.as<double>(), nullptr, nullptr, fnorm2, partial, partial_cap,
-                            nullptr, st));
+    HIP_TRY(launch_residual(X32, ldx32, m, n, y, nullptr, a_out, nullptr, fnorm2, partial, partial_cap, nullptr, st));
   HIP_TRY(hipEventRecord(c->ev[3], st));
-  CtlBlock* hc = reinterpret_cast<CtlBlock*>(c->host);
-  double* hh = reinterpret_cast<double*>(reinterpret_cast<char*>(c->host) + sizeof(CtlBlock));
+  CtlBlock* hc = ho.cb;
+  double* hh = ho.hist;
   HIP_TRY(hipMemcpyAsync(hc, cb, sizeof(CtlBlock), hipMemcpyDeviceToHost, st));
-  if (hist) HIP_TRY(hipMemcpyAsync(hh, c->hist.p, (size_t)hist_len * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(hh, w.hist, (size_t)hist_len * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
 
-  if (hist) std::memcpy(hist, hh, (size_t)hist_len * 8);
+  if (hist && hist != hh) std::memcpy(hist, hh, (size_t)hist_len * 8);
   if (info) {
     std::memset(info, 0, sizeof *info);
     info->sweeps_done = hc->ctl[CTL_SWEEPS];
@@ -455,6 +539,10 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
     info->sweep_ms = elapsed(c->ev[1], c->ev[2]);
     info->total_ms = elapsed(c->ev[0], c->ev[3]);
     info->kernel_kind = pl.D;
+    // ||e|| grew over a sweep (by more than 0.1 %)
+    for (int32_t k = 1; k <= info->sweeps_done && k < hist_len; ++k)
+      if (hh[k] > hh[k - 1] * 1.001) info->diverged = 1;
+    info->rel_grad = (grad_rule && info->sweeps_done > 0) ? hc->fstat[2] : std::numeric_limits<double>::quiet_NaN();
   }
   if (hc->ctl[CTL_NONFINITE]) return fail(HPSCD_ENONFINITE, "X or y holds a non-finite value");
   if (hc->ctl[CTL_ERR] == ERR_TIMEOUT) return fail(HPSCD_ETIMEOUT, "grid reduction timed out");
@@ -462,6 +550,29 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   if (hc->ctl[CTL_ERR] == ERR_NONFINITE) return fail(HPSCD_ENONFINITE, "the iteration produced a non-finite residual");
   g_err.clear();
   return HPSCD_OK;
+}
+
+// Plan, size the context's workspace and solve.
+hpscd_status solve_single_ctx(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, int64_t ldxs, bool bf16,
+                              const float* X32, int64_t ldx32, const float* y, const float* a0, const hpscd_opts* o,
+                              float* a_out, double* hist, hpscd_info* info, hipStream_t st) {
+  hpscd_opts oo = *o;
+  if (oo.max_sweeps == 0) oo.order = nullptr;  // (no sweep: the order is not read)
+  o = &oo;
+  Plan pl;
+  hpscd_status rc = plan_single(c, m, n, bf16, o, &pl);
+  if (rc != HPSCD_OK) return rc;
+  HIP_TRY(hipSetDevice(c->device));
+  if (pl.V == 2 && n * (int64_t)(ldxs * 4) > (int64_t)0xFFFFFFFF)
+    return fail(HPSCD_EINVAL, "a column order needs X below 4 GiB");
+  const WorkSizes z = work_sizes(pl, m, n, o);
+  Work w;
+  if ((rc = work_from_ctx(c, z, &w)) != HPSCD_OK) return rc;
+  const int64_t hist_len = (int64_t)o->max_sweeps + 1;
+  if ((rc = c->host_ensure(sizeof(CtlBlock) + (size_t)hist_len * 8))) return rc;
+  HostOut ho{reinterpret_cast<CtlBlock*>(c->host),
+             reinterpret_cast<double*>(reinterpret_cast<char*>(c->host) + sizeof(CtlBlock))};
+  return solve_single(c, m, n, Xs, ldxs, bf16, X32, ldx32, y, a0, o, a_out, hist, info, st, pl, w, ho);
 }
 
 }  // namespace
@@ -510,7 +621,8 @@ void hpscd_destroy(hpscd_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
-  for (DevBuf* b : {&c->ctlb, &c->e0, &c->eo, &c->a64, &c->rdn, &c->gram, &c->cross, &c->partial, &c->slots, &c->hist})
+  for (DevBuf* b : {&c->ctlb, &c->e0, &c->eo, &c->a64, &c->rdn, &c->gram, &c->cross, &c->partial, &c->slots, &c->hist,
+                    &c->selw})
     b->release();
   c->bw.release();
   if (c->host) (void)hipHostFree(c->host);
@@ -532,7 +644,7 @@ hpscd_status hpscd_solve_f32(hpscd_ctx* ctx, int64_t m, int64_t n, const float* 
     hpscd_status rc = validate_single(m, n, X, ldx, 4, y, opts, a_out);
     if (rc != HPSCD_OK) return rc;
     if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
-    return solve_single(ctx, m, n, X, ldx, false, X, ldx, y, a0, opts, a_out, hist, info, (hipStream_t)stream);
+    return solve_single_ctx(ctx, m, n, X, ldx, false, X, ldx, y, a0, opts, a_out, hist, info, (hipStream_t)stream);
   } catch (...) {
     return fail(HPSCD_ENOMEM, "host allocation failure");
   }
@@ -548,7 +660,7 @@ hpscd_status hpscd_solve_bf16(hpscd_ctx* ctx, int64_t m, int64_t n, const uint16
     if (ldx < m || ldx % 4 != 0 || !aligned16(X32))
       return fail(HPSCD_EINVAL, "X32 needs ldx >= m, ldx %% 4 == 0 and 16-byte alignment");
     if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
-    return solve_single(ctx, m, n, Xb, ldxb, true, X32, ldx, y, a0, opts, a_out, hist, info, (hipStream_t)stream);
+    return solve_single_ctx(ctx, m, n, Xb, ldxb, true, X32, ldx, y, a0, opts, a_out, hist, info, (hipStream_t)stream);
   } catch (...) {
     return fail(HPSCD_ENOMEM, "host allocation failure");
   }
@@ -586,6 +698,113 @@ hpscd_status hpscd_residual_f64(hpscd_ctx* ctx, int64_t m, int64_t n, const floa
     *norm_out = std::sqrt(*reinterpret_cast<double*>(ctx->host));
   }
   return HPSCD_OK;
+}
+
+hpscd_status hpscd_select_f32(hpscd_ctx* ctx, int64_t m, int64_t n, const float* X, int64_t ldx, const float* y,
+                              const float* a0, int32_t F, double tol, float* a_out, int32_t* J_out,
+                              double* da_out, double* hist, int32_t* selected, void* stream) {
+  try {
+    if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
+    if (m < 1 || n < 1) return fail(HPSCD_EINVAL, "m and n must be >= 1");
+    if (!X || !y || !a_out) return fail(HPSCD_EINVAL, "X, y and a_out must not be NULL");
+    if (!J_out || !selected) return fail(HPSCD_EINVAL, "J_out and selected must not be NULL");
+    if (ldx < m || ldx % 4 != 0 || !aligned16(X))
+      return fail(HPSCD_EINVAL, "X needs ldx >= m, ldx %% 4 == 0 and 16-byte alignment");
+    if (F < 0) return fail(HPSCD_EINVAL, "F must be >= 0");
+    if (!std::isfinite(tol) || tol < 0.0) return fail(HPSCD_EINVAL, "tol must be finite and >= 0");
+    if (n > (int64_t)65535 * 64) return fail(HPSCD_EINVAL, "n above %lld", (long long)65535 * 64);
+    if (m > (int64_t)1 << 40) return fail(HPSCD_EINVAL, "system too large");
+    hipStream_t st = (hipStream_t)stream;
+    hpscd_ctx* c = ctx;
+    HIP_TRY(hipSetDevice(c->device));
+    const int32_t Fe = (int32_t)std::min<int64_t>(F, n);
+    // workspace: the column statistics and the residual passes share the
+    // partial sums with X^T e
+    int64_t cap = std::max<int64_t>({(int64_t)1 << 21, n * 80, (m + 1023) / 1024 + 8});
+    const XtvPlan xp = plan_xtv(m, n, cap);
+    cap = std::max<int64_t>(cap, xp.need);
+    hpscd_status rc;
+    if ((rc = ensure(c->ctlb, sizeof(CtlBlock), "ctl")) || (rc = ensure(c->a64, (size_t)n * 8, "a64")) ||
+        (rc = ensure(c->rdn, (size_t)n * 8, "rdn")) || (rc = ensure(c->gram, 8, "gram")) ||
+        (rc = ensure(c->partial, (size_t)cap * 8, "partial")))
+      return rc;
+    // selection region: e64[m], g[n], tscore[T], tidx[T], flags[n], J[F], da[F], hist[F+1], part[m/1024+1],
+    // step (j, da), final norm
+    const int64_t nparts = (m + 1023) / 1024;
+    auto al = [](int64_t b) { return (b + 255) / 256 * 256; };
+    const int64_t o_e = 0, o_g = o_e + al(m * 8), o_ts = o_g + al(n * 8), o_ti = o_ts + al(xp.T * 8),
+                  o_fl = o_ti + al(xp.T * 8), o_J = o_fl + al(n * 4), o_da = o_J + al((int64_t)Fe * 4 + 4),
+                  o_h = o_da + al((int64_t)Fe * 8 + 8), o_p = o_h + al(((int64_t)Fe + 1) * 8), o_s = o_p + al(nparts * 8),
+                  o_end = o_s + 256;
+    if ((rc = ensure(c->selw, (size_t)o_end, "selection workspace"))) return rc;
+    const size_t host_bytes = sizeof(CtlBlock) + ((size_t)Fe + 1) * 8 * 2 + (size_t)Fe * 4 + 64;
+    if ((rc = c->host_ensure(host_bytes))) return rc;
+    char* sw = reinterpret_cast<char*>(c->selw.p);
+    double* e64 = reinterpret_cast<double*>(sw + o_e);
+    double* g = reinterpret_cast<double*>(sw + o_g);
+    double* tsc = reinterpret_cast<double*>(sw + o_ts);
+    int64_t* tid = reinterpret_cast<int64_t*>(sw + o_ti);
+    int32_t* flags = reinterpret_cast<int32_t*>(sw + o_fl);
+    int32_t* Jd = reinterpret_cast<int32_t*>(sw + o_J);
+    double* dad = reinterpret_cast<double*>(sw + o_da);
+    double* hd = reinterpret_cast<double*>(sw + o_h);
+    double* parts = reinterpret_cast<double*>(sw + o_p);
+    int64_t* step_j = reinterpret_cast<int64_t*>(sw + o_s);
+    double* step_da = reinterpret_cast<double*>(sw + o_s + 8);
+    double* fin = reinterpret_cast<double*>(sw + o_s + 16);
+    CtlBlock* cb = c->ctlb.as<CtlBlock>();
+    int32_t* ctl = reinterpret_cast<int32_t*>(cb);
+    int64_t* ctl64 = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(cb) + offsetof(CtlBlock, ctl64));
+    double* ynorm2 = reinterpret_cast<double*>(reinterpret_cast<char*>(cb) + offsetof(CtlBlock, ynorm2));
+    double* partial = c->partial.as<double>();
+    const int64_t pcap = (int64_t)(c->partial.cap / 8);
+
+    HIP_TRY(launch_fill_i32(ctl, sizeof(CtlBlock) / 4, 0, st));
+    HIP_TRY(launch_fill_i32(flags, n, 0, st));
+    HIP_TRY(launch_fill_i32(Jd, Fe + 1, -1, st));
+    HIP_TRY(launch_fill_f64(hd, Fe + 1, std::numeric_limits<double>::quiet_NaN(), st));
+    HIP_TRY(launch_a_init(c->a64.as<double>(), a0, n, st));
+    HIP_TRY(launch_residual(X, ldx, m, 0, y, nullptr, nullptr, nullptr, ynorm2, partial, pcap, nullptr, st));
+    // <X_j, X_j> (as 1/<X_j, X_j>, 0 for a zero column) with FP64 sums
+    HIP_TRY(launch_colgram(X, false, ldx, m, n, 1, c->rdn.as<double>(), c->gram.as<double>(), nullptr, partial, pcap,
+                           ctl, &ctl64[C64_ZERO_COLS], st));
+    if (a0)
+      HIP_TRY(launch_residual(X, ldx, m, n, y, nullptr, a0, nullptr, nullptr, partial, pcap, nullptr, st, e64));
+    else
+      HIP_TRY(launch_to_f64(y, e64, m, st));
+    for (int32_t f = 0; f < Fe; ++f)
+      HIP_TRY(launch_select_step(X, ldx, m, n, e64, xp, partial, partial + xp.S * n, g, tsc, tid, c->rdn.as<double>(),
+                                 f, tol, flags, c->a64.as<double>(), Jd, dad, hd, ctl, step_j, step_da, st));
+    HIP_TRY(launch_norm_f64(e64, m, parts, fin, st));
+    HIP_TRY(launch_a_out(c->a64.as<double>(), a_out, n, st));
+    char* h = reinterpret_cast<char*>(c->host);
+    CtlBlock* hcb = reinterpret_cast<CtlBlock*>(h);
+    double* hh = reinterpret_cast<double*>(h + sizeof(CtlBlock));
+    double* hda = hh + Fe + 1;
+    int32_t* hJ = reinterpret_cast<int32_t*>(hda + Fe + 1);
+    double* hfin = reinterpret_cast<double*>(hJ + Fe + 2);
+    HIP_TRY(hipMemcpyAsync(hcb, cb, sizeof(CtlBlock), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hh, hd, ((size_t)Fe + 1) * 8, hipMemcpyDeviceToHost, st));
+    if (Fe > 0) HIP_TRY(hipMemcpyAsync(hda, dad, (size_t)Fe * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hJ, Jd, ((size_t)Fe + 1) * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hfin, fin, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hcb->ctl[CTL_NONFINITE] || !(hcb->ynorm2 <= DBL_MAX))
+      return fail(HPSCD_ENONFINITE, "X or y holds a non-finite value");
+    const int32_t cnt = hcb->ctl[CTL_SWEEPS];
+    *selected = cnt;
+    for (int32_t f = 0; f < F; ++f) J_out[f] = f < cnt ? hJ[f] : -1;
+    if (da_out)
+      for (int32_t f = 0; f < F; ++f) da_out[f] = f < cnt ? hda[f] : std::numeric_limits<double>::quiet_NaN();
+    if (hist) {
+      for (int32_t f = 0; f <= F; ++f) hist[f] = f < cnt ? hh[f] : std::numeric_limits<double>::quiet_NaN();
+      hist[cnt] = *hfin;
+    }
+    g_err.clear();
+    return HPSCD_OK;
+  } catch (...) {
+    return fail(HPSCD_ENOMEM, "host allocation failure");
+  }
 }
 
 hpscd_status hpscd_abort(hpscd_ctx* ctx) {
@@ -780,7 +999,7 @@ hpscd_status enqueue_batch(hpscd_ctx* c, BatchWork& w, const BatchPlan& bp, cons
   if (ev) HIP_TRY(hipEventRecord(ev[2], st));
   HIP_TRY(launch_a_out_batched(w.a64.as<double>(), apool, dsys, count, st));
   if (!(o->flags & HPSCD_F_NO_FINAL_CHECK))
-    HIP_TRY(launch_residual_batched(Xpool, ypool, dsys, count, w.a64.as<double>(), nullptr, nullptr, fnorm2, st));
+    HIP_TRY(launch_residual_batched(Xpool, ypool, dsys, count, nullptr, apool, nullptr, fnorm2, st));
   if (ev) HIP_TRY(hipEventRecord(ev[3], st));
   return HPSCD_OK;
 }

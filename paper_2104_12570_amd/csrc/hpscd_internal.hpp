@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct hpscd_ctx;
+
 namespace hpscd {
 
 // Arguments of one sweep-kernel launch (single system, grid or one workgroup).
@@ -12,7 +14,6 @@ struct SolveArgs {
   const float* e0;        // residual at entry (length m)
   const double* rdn;      // [nb*B] 1/<X_j,X_j> (0 for zero and padding columns)
   const double* gram;     // [nb][B*(B-1)/2] strictly-lower in-block Gram, (l,i) row-major
-  const double* cross;    // [nb][B*B] Gram with the previous block (pipelined kernel only)
   const double* minv;     // [nb][B][B] step matrix M = (D+L)^-1 of each block, row-major (B = 16 only)
   double* a64;            // [n] coefficients, accumulated in FP64
   float* e_out;           // [m] residual at exit
@@ -32,6 +33,8 @@ struct SolveArgs {
   int32_t rows_per_wg;    // rows owned by one workgroup (wide-block kernel; others own T*R*VEC)
   uint64_t timeout_ticks; // bound on any spin-wait (100 MHz ticks)
   uint32_t poll_delay;    // ticks between publishing and the first poll of a grid reduction
+  int32_t thr;            // Algorithm 2 block width (wide-block kernel, variant 1)
+  const int32_t* order;   // [max_sweeps][n] column order (wide-block kernel, variant 2)
 };
 
 // One system of a batch as the batched kernels see it (element offsets).
@@ -72,15 +75,18 @@ struct BatchArgs {
 
 // Message returned by hpscd_last_error() on this host thread.
 void set_last_error(const char* msg);
+// HIP device of a context.
+int ctx_device(const struct ::hpscd_ctx* c);
 
 // Kernel launchers (return hipError_t of the launch).
-// D: kernel kind: 2, 3 = prefetch ring of 2 or 3 blocks; 4 = pipelined reductions;
-// 12, 13 = warp-specialised with a ring of 2 or 3 blocks; 0 = any.
+// D: kernel kind (2, 3, 4: k_sweep ring; 5: k_sweep_px; 8: k_sweep_wide).
+// V: method variant of the wide-block kernel (0: Algorithm 1, 1: Algorithm 2
+// with SolveArgs::thr, 2: column order SolveArgs::order); 0 for other kinds.
 hipError_t launch_sweep(int variant_T, int variant_R, int B, bool bf16, bool grid, int D,
-                        const SolveArgs& a, hipStream_t s, bool cooperative);
-int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid, int D);
-int sweep_max_workgroups(int T, int R, int B, bool bf16, bool grid, int D);
-bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid, int D);
+                        const SolveArgs& a, hipStream_t s, bool cooperative, int V = 0);
+int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid, int D, int V = 0);
+int sweep_max_workgroups(int T, int R, int B, bool bf16, bool grid, int D, int V = 0);
+bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid, int D, int V = 0);
 
 hipError_t launch_batched(int B, const BatchArgs& a, int grid, hipStream_t s);
 int batched_threads(int code);
@@ -98,9 +104,15 @@ bool batched_variant_exists(int code);
 // cross: NULL, or [nb][B*B] receiving <X_{b,l}, X_{b-1,i}> at l*B + i (zero for b = 0).
 // B = 16: cross is required and receives each block's step matrix M (see
 // k_block_inverse16) instead.
+// map: NULL, or (B = 16, FP32 only) the column order of the sweep: block
+// position p holds column map[p]; the kernels return at once while
+// ctl[CTL_DONE] is set (a solve that has stopped).  thr > 1 (B = 16, FP32):
+// the step matrices of Algorithm 2 with blocks of thr columns instead of
+// those of Algorithm 1.  zero_cols: NULL or the counter of zero columns.
 hipError_t launch_colgram(const void* X, bool bf16, int64_t ldx, int64_t m, int64_t n, int B,
                           double* rdn, double* gram, double* cross, double* partial, int64_t partial_cap,
-                          int32_t* ctl, int64_t* zero_cols, hipStream_t s);
+                          int32_t* ctl, int64_t* zero_cols, hipStream_t s, const int32_t* map = nullptr,
+                          int32_t thr = 0);
 hipError_t launch_colgram_batched(const float* Xpool, const SysDesc* sys, int32_t count, int64_t nblk_total,
                                   const int64_t* blk_first, int B, double* rdn, double* gram,
                                   int32_t* ctl, hipStream_t s);
@@ -108,7 +120,30 @@ hipError_t launch_colgram_batched(const float* Xpool, const SysDesc* sys, int32_
 // ||r||^2 into *norm2 (device double).
 hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t ncols, const float* y,
                            const double* a64, const float* a32, float* e_out, double* norm2,
-                           double* partial, int64_t partial_cap, const int32_t* skip_if, hipStream_t s);
+                           double* partial, int64_t partial_cap, const int32_t* skip_if, hipStream_t s,
+                           double* e64_out = nullptr);
+
+// X^T v for all n columns (FP64 sums): S row strips of rows_per rows, G
+// groups of 64 columns, T tiles of 256 columns; `need` doubles of workspace.
+struct XtvPlan {
+  int64_t S, G, T, rows_per, need;
+};
+XtvPlan plan_xtv(int64_t m, int64_t n, int64_t cap);
+hipError_t launch_xtv(const float* X, int64_t ldx, int64_t m, int64_t n, const void* v, bool v_f64,
+                      const XtvPlan& p, double* partial, double* vnorm, const int32_t* done, hipStream_t s);
+// Gradient stop rule after sweep `sweep` on the running residual e (or, with
+// init, ||X^T y||^2 from e = y).  ws: workspace of cap doubles.
+hipError_t launch_grad_stop(const float* X, int64_t ldx, int64_t m, int64_t n, const float* e, bool init,
+                            int32_t sweep, double tol, double* ws, int64_t cap, int32_t* ctl, int64_t* ctl64,
+                            double* fstat, double* hist, hipStream_t s);
+// One selection step of Algorithm 3 (see hpscd_select.hip).
+hipError_t launch_select_step(const float* X, int64_t ldx, int64_t m, int64_t n, double* e, const XtvPlan& p,
+                              double* partial, double* vnorm, double* g, double* tscore, int64_t* tidx,
+                              const double* rdn, int32_t f, double tol, int32_t* selected, double* a64, int32_t* Jd,
+                              double* dad, double* hist, int32_t* ctl, int64_t* step_j, double* step_da,
+                              hipStream_t s);
+hipError_t launch_norm_f64(const double* e, int64_t m, double* part, double* out, hipStream_t s);
+hipError_t launch_to_f64(const float* src, double* dst, int64_t m, hipStream_t s);
 hipError_t launch_residual_batched(const float* Xpool, const float* ypool, const SysDesc* sys, int32_t count,
                                    const double* a64pool, const float* a32pool, float* e_out,
                                    double* norm2, hipStream_t s);

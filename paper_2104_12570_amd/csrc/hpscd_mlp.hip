@@ -119,11 +119,16 @@ __global__ void k_colsum(const float* G, int rows, int cols, float* out) {
 
 // Output gradient of the loss L = sum_{b,k} (o - t)^2 / (batch * out):
 // dO = 2 (o - t) / (batch * out); per-block partial sums of (o - t)^2.
-__global__ void k_mse(const float* O, const float* Tt, float* dO, int64_t n, float scale, float* part) {
+// The target enters standardised per output column k = i mod out:
+// (t - mu_k) / sd_k with osc = [mu (out), sd (out)] (mu 0, sd 1 until an
+// output scaling is fitted).
+__global__ void k_mse(const float* O, const float* Tt, float* dO, int64_t n, float scale, float* part,
+                      const float* osc, int out) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   float d = 0.f;
   if (i < n) {
-    d = O[i] - Tt[i];
+    const int k = (int)(i % out);
+    d = O[i] - (Tt[i] - osc[k]) / osc[out + k];
     dO[i] = 2.f * d * scale;
   }
   __shared__ float ws[4];
@@ -143,6 +148,48 @@ __global__ void k_sum_f32(const float* v, int n, float* out, float scale) {
   if (threadIdx.x == 0) *out = ((ws[0] + ws[1]) + (ws[2] + ws[3])) * scale;
 }
 
+// Network output in target units: y = sd_k * o + mu_k.
+__global__ void k_affine_out(const float* O, float* Y, int64_t n, const float* osc, int out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int k = (int)(i % out);
+  Y[i] = fmaf(osc[out + k], O[i], osc[k]);
+}
+
+// Output scaling from targets T[count][out]: per column k the mean and the
+// sample standard deviation (two passes, FP64 sums; at least 1e-12; 1 for a
+// single row).  One workgroup per column.
+__global__ void __launch_bounds__(256) k_colstats(const float* T, int64_t count, int out, float* osc) {
+  const int k = blockIdx.x;
+  __shared__ double ws[4];
+  double acc = 0.0;
+  for (int64_t b = threadIdx.x; b < count; b += 256) acc += (double)T[b * out + k];
+  double t = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
+  __syncthreads();
+  const double mean = ((ws[0] + ws[1]) + (ws[2] + ws[3])) / (double)count;
+  __syncthreads();
+  acc = 0.0;
+  for (int64_t b = threadIdx.x; b < count; b += 256) {
+    const double d = (double)T[b * out + k] - mean;
+    acc = fma(d, d, acc);
+  }
+  t = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double ss = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+    const double sd = count > 1 ? sqrt(ss / (double)(count - 1)) : 1.0;
+    osc[k] = (float)mean;
+    osc[out + k] = (float)(sd > 1e-12 ? sd : 1e-12);
+  }
+}
+
+__global__ void k_osc_reset(float* osc, int out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < 2 * out) osc[i] = i < out ? 0.f : 1.f;
+}
+
 // Adam (Kingma & Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
 // p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
@@ -159,6 +206,25 @@ __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 
 static inline dim3 g1(int64_t n) { return dim3((unsigned)std::max<int64_t>(1, (n + 255) / 256)); }
 
+// Parameters k0 .. k0+count-1 of the flat vector drawn uniform in
+// [-bound, bound): value k of the SplitMix64 stream started at `seed`
+// (Steele, Lea and Flood, "Fast splittable pseudorandom number generators",
+// 2014: state_k = seed + (k+1)*0x9E3779B97F4A7C15, then the finaliser of
+// Stafford's Mix13), its top 53 bits taken as u in [0, 1).
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_init_uniform(float* p, int64_t k0, int64_t count, double bound, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const double u = (double)(splitmix64_at(seed, (uint64_t)(k0 + i)) >> 11) * 0x1.0p-53;
+  p[k0 + i] = (float)((2.0 * u - 1.0) * bound);
+}
+
 }  // namespace mlp
 }  // namespace hpscd
 
@@ -174,6 +240,7 @@ struct hpscd_mlp {
   float *z1 = nullptr, *a1 = nullptr, *z2 = nullptr, *a2 = nullptr, *o = nullptr;
   float *d3 = nullptr, *d2 = nullptr, *d1 = nullptr, *part = nullptr, *loss = nullptr;
   float* host_loss = nullptr;
+  float* osc = nullptr;  // output scaling [mu (out), sd (out)]
   int64_t t = 0;  // Adam step count
 
   float* W1() { return p; }
@@ -229,7 +296,7 @@ hpscd_status forward(hpscd_mlp* n, int batch, const float* x, hipStream_t s) {
 hpscd_status backward(hpscd_mlp* n, int batch, const float* x, const float* target, hipStream_t s) {
   const int64_t no = (int64_t)batch * n->out;
   const float scale = 1.0f / (float)((int64_t)batch * n->out);
-  hipLaunchKernelGGL(k_mse, g1(no), dim3(256), 0, s, n->o, target, n->d3, no, scale, n->part);
+  hipLaunchKernelGGL(k_mse, g1(no), dim3(256), 0, s, n->o, target, n->d3, no, scale, n->part, n->osc, n->out);
   hipLaunchKernelGGL(k_sum_f32, dim3(1), dim3(256), 0, s, n->part, (int)g1(no).x, n->loss, scale);
   float* gW1 = n->g;
   float* gB1 = gW1 + (int64_t)n->h1 * n->in;
@@ -273,14 +340,13 @@ hpscd_status read_loss(hpscd_mlp* n, float* loss_out, hipStream_t s) {
 
 extern "C" {
 
-hpscd_status hpscd_mlp_create(int device, int in, int h1, int h2, int out, hpscd_mlp** res) {
+hpscd_status hpscd_mlp_create(hpscd_ctx* ctx, int in, int h1, int h2, int out, uint64_t seed, hpscd_mlp** res) {
   if (!res) return mfail(HPSCD_EINVAL, "out pointer is NULL");
   *res = nullptr;
+  if (!ctx) return mfail(HPSCD_EINVAL, "ctx is NULL");
   if (in < 1 || h1 < 1 || h2 < 1 || out < 1 || in > 65536 || h1 > 65536 || h2 > 65536 || out > 65536)
     return mfail(HPSCD_EINVAL, "layer widths must be in [1, 65536]");
-  int count = 0;
-  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
-    return mfail(HPSCD_EDEVICE, "no such HIP device");
+  const int device = hpscd::ctx_device(ctx);
   MLP_TRY(hipSetDevice(device));
   hpscd_mlp* n = new hpscd_mlp();
   n->dev = device;
@@ -288,14 +354,24 @@ hpscd_status hpscd_mlp_create(int device, int in, int h1, int h2, int out, hpscd
   n->np = nparams(in, h1, h2, out);
   for (float** b : {&n->p, &n->g, &n->m, &n->v})
     if (hipMalloc(b, n->np * sizeof(float)) != hipSuccess) { hpscd_mlp_destroy(n); return mfail(HPSCD_ENOMEM, "params"); }
-  if (hipMalloc(&n->loss, sizeof(float)) != hipSuccess ||
+  if (hipMalloc(&n->loss, sizeof(float)) != hipSuccess || hipMalloc(&n->osc, 2 * (size_t)out * sizeof(float)) != hipSuccess ||
       hipHostMalloc(&n->host_loss, sizeof(float), hipHostMallocDefault) != hipSuccess) {
     hpscd_mlp_destroy(n);
     return mfail(HPSCD_ENOMEM, "loss");
   }
-  MLP_TRY(hipMemset(n->p, 0, n->np * sizeof(float)));
   MLP_TRY(hipMemset(n->m, 0, n->np * sizeof(float)));
   MLP_TRY(hipMemset(n->v, 0, n->np * sizeof(float)));
+  hipLaunchKernelGGL(k_osc_reset, g1(2 * (int64_t)out), dim3(256), 0, 0, n->osc, out);
+  // W and b of each layer uniform in +-1/sqrt(fan_in), in the flat order
+  const int fan[3] = {in, h1, h2}, rows[3] = {h1, h2, out};
+  int64_t k0 = 0;
+  for (int l = 0; l < 3; ++l) {
+    const int64_t cnt = (int64_t)rows[l] * fan[l] + rows[l];
+    hipLaunchKernelGGL(k_init_uniform, g1(cnt), dim3(256), 0, 0, n->p, k0, cnt, 1.0 / std::sqrt((double)fan[l]), seed);
+    k0 += cnt;
+  }
+  MLP_TRY(hipGetLastError());
+  MLP_TRY(hipDeviceSynchronize());
   *res = n;
   return HPSCD_OK;
 }
@@ -304,7 +380,8 @@ void hpscd_mlp_destroy(hpscd_mlp* n) {
   if (!n) return;
   (void)hipSetDevice(n->dev);
   (void)hipDeviceSynchronize();
-  for (float* b : {n->p, n->g, n->m, n->v, n->z1, n->a1, n->z2, n->a2, n->o, n->d3, n->d2, n->d1, n->part, n->loss})
+  for (float* b : {n->p, n->g, n->m, n->v, n->z1, n->a1, n->z2, n->a2, n->o, n->d3, n->d2, n->d1, n->part, n->loss,
+                   n->osc})
     if (b) (void)hipFree(b);
   if (n->host_loss) (void)hipHostFree(n->host_loss);
   delete n;
@@ -335,7 +412,33 @@ hpscd_status hpscd_mlp_forward(hpscd_mlp* n, int batch, const float* x, float* y
   if ((rc = ensure_batch(n, batch)) != HPSCD_OK) return rc;
   hipStream_t s = (hipStream_t)stream;
   if ((rc = forward(n, batch, x, s)) != HPSCD_OK) return rc;
-  MLP_TRY(hipMemcpyAsync(y, n->o, (size_t)batch * n->out * sizeof(float), hipMemcpyDeviceToDevice, s));
+  const int64_t no = (int64_t)batch * n->out;
+  hipLaunchKernelGGL(k_affine_out, g1(no), dim3(256), 0, s, n->o, y, no, n->osc, n->out);
+  MLP_TRY(hipGetLastError());
+  return HPSCD_OK;
+}
+
+hpscd_status hpscd_mlp_fit_output_scaling(hpscd_mlp* n, int count, const float* target, void* stream) {
+  if (!n || !target) return mfail(HPSCD_EINVAL, "NULL argument");
+  if (count < 1) return mfail(HPSCD_EINVAL, "count must be >= 1");
+  MLP_TRY(hipSetDevice(n->dev));
+  hipLaunchKernelGGL(k_colstats, dim3(n->out), dim3(256), 0, (hipStream_t)stream, target, (int64_t)count, n->out,
+                     n->osc);
+  MLP_TRY(hipGetLastError());
+  return HPSCD_OK;
+}
+
+hpscd_status hpscd_mlp_get_output_scaling(hpscd_mlp* n, float* mu_sd, void* stream) {
+  if (!n || !mu_sd) return mfail(HPSCD_EINVAL, "NULL argument");
+  MLP_TRY(hipMemcpyAsync(mu_sd, n->osc, 2 * (size_t)n->out * sizeof(float), hipMemcpyDeviceToDevice,
+                         (hipStream_t)stream));
+  return HPSCD_OK;
+}
+
+hpscd_status hpscd_mlp_set_output_scaling(hpscd_mlp* n, const float* mu_sd, void* stream) {
+  if (!n || !mu_sd) return mfail(HPSCD_EINVAL, "NULL argument");
+  MLP_TRY(hipMemcpyAsync(n->osc, mu_sd, 2 * (size_t)n->out * sizeof(float), hipMemcpyDeviceToDevice,
+                         (hipStream_t)stream));
   return HPSCD_OK;
 }
 

@@ -741,502 +741,17 @@ __global__ void __launch_bounds__(T) k_sweep_px(SolveArgs A) {
       if (i < lim[c]) A.e_out[rof[c] + i] = e[c][i];
 }
 
-// --------------------------------------------------------------------------
-// Grid kernel with a polling wave and a ring of D column blocks.
-//
-// The waves of a workgroup split into NH = NW - 1 streaming waves and one
-// polling wave that run separate loops, meeting at the same three barriers
-// per block, so each loop holds only its own registers:
-//  * a streaming wave keeps a ring of D register blocks.  It requests a
-//    block as soon as the buffer that will hold it is free (right after the
-//    axpy of the block D steps earlier), so the next D - 1 blocks are in
-//    flight while the current one is reduced: a block has D - 1 steps to
-//    arrive.  It also loads a share of the polling wave's rows and, once
-//    they have landed, copies them to LDS (plain loads: direct-to-LDS loads
-//    of those rows cost the column stream about a third of its rate).
-//    Column loads are its only vector memory operations, so it waits for the
-//    block it is about to use with an explicit count of the operations
-//    issued after that block (its share of the polling wave's rows is taken
-//    at its minimum: the wait may be slightly longer, never shorter).
-//  * the polling wave issues no column loads, so its polls of the exchange
-//    words never queue behind column data.  It takes its rows from LDS,
-//    publishes the workgroup's partial sums, sums the other workgroups',
-//    runs the stop tests and the forward substitution, and hands the
-//    block's steps da to the streaming waves through LDS.
-// The barriers order LDS only (an LDS wait and s_barrier): a barrier with
-// memory fences would also wait for the column loads in flight.
-// Arithmetic, reduction order and stop logic are those of k_sweep.
 // First row of a chunk that holds only rows below m, read in place of a
 // chunk with no valid row (finite data, whose residual is held at zero).
 // With m below one chunk there is none: every chunk is then masked.
 __device__ inline int64_t full_chunk_row(int64_t m, int vec) { return m >= vec ? (m / vec - 1) * vec : 0; }
 
+// Barrier that orders LDS only (an LDS wait and s_barrier): a barrier with
+// memory fences would also wait for the column loads in flight.
 __device__ inline void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   __builtin_amdgcn_s_barrier();
   asm volatile("" ::: "memory");
-}
-
-// Keeps the memory operations before it before it and those after it after
-// it, both in the compiler's IR and in its instruction scheduling.
-__device__ inline void pin_order() {
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_sched_barrier(0);
-}
-
-template <int N>
-__device__ inline void wait_vm_at_most() {
-  static_assert(N >= 0 && N <= 63, "vmcnt range");
-  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
-}
-
-template <class S, int T, int R, int B, int D>
-__global__ void __launch_bounds__(T) k_sweep_pe(SolveArgs A) {
-  using raw = typename S::raw_t;
-  constexpr int VEC = S::VEC;
-  constexpr int NW = T / WAVE;
-  constexpr int NV = B + 1;
-  constexpr int NH = NW - 1;                         // waves that stream columns
-  constexpr int MAXC = 4;                            // up to 256 workgroups
-  constexpr int U = B * R;                           // chunks of the poller's rows per block
-  constexpr int UPW = (U + NH - 1) / NH;             // ... loaded by one streaming wave, at most
-  constexpr int UMIN = U / NH;                       // ... and at least
-  constexpr int OPS_MIN = B * R + UMIN;              // vector memory operations per block and streaming wave
-  constexpr int WAIT_N = (D - 1) * OPS_MIN < 63 ? (D - 1) * OPS_MIN : 63;
-  static_assert(NW >= 2 && (D == 2 || D == 3), "wave split, ring depth");
-  using pbuf_t = raw[B][R][WAVE];
-  constexpr int NG = B * (B - 1) / 2;
-  constexpr int MAXCOEF = 8192;  // coefficient table held in LDS up to this many doubles
-  constexpr int MAXOWN = 512;    // a_j of the columns this workgroup owns, held in LDS up to this many
-  __shared__ float red[NW][NV];
-  __shared__ pbuf_t pbuf;  // the polling wave's rows of the current block
-  __shared__ double sda[B];
-  __shared__ int sstop;
-  __shared__ double scoef[MAXCOEF];
-  __shared__ double sown[MAXOWN];
-
-  const int tid = threadIdx.x, lane = tid & (WAVE - 1);
-  const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
-  const bool pollw = wave == NH;
-  const int wg = (int)blockIdx.x;
-  const int64_t m = A.m, n = A.n;
-  const int nb = (int)((n + B - 1) / B);
-  if (A.ctl[CTL_NONFINITE] != 0 || A.ctl[CTL_DONE] != 0) return;
-
-  float e[R][VEC];
-  int lim[R];
-#pragma unroll
-  for (int c = 0; c < R; ++c) {
-    const int64_t r0 = (int64_t)wg * (T * R * VEC) + (int64_t)VEC * (tid + T * c);
-    const int64_t left = m - r0;
-    lim[c] = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
-#pragma unroll
-    for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? A.e0[r0 + i] : 0.f;
-  }
-  const int64_t nblocks = A.blk_end - A.blk_begin;
-  const int64_t col_bytes = A.ldx * (int64_t)(16 / VEC);
-  // Rows past m: a chunk with no valid row is read from a chunk of valid
-  // rows instead (its residual is held at zero), and the one chunk of the
-  // system that straddles m is masked element by element (every chunk when
-  // m is below one chunk).
-  const bool ragged = (int64_t)(wg + 1) * (T * R * VEC) > m;  // the workgroup holding the last rows
-  const bool tiny = m < VEC;
-  const int64_t safe_row = full_chunk_row(m, VEC);
-  bool straddle[R];
-#pragma unroll
-  for (int c = 0; c < R; ++c) straddle[c] = __ballot(lim[c] < VEC && (lim[c] > 0 || tiny)) != 0;
-
-  // Partial sums of the block (B dots against the block-start residual and
-  // ||e||^2) of this wave's rows, to LDS.
-  auto partials = [&](raw (&xl)[B][R]) {
-#pragma unroll
-    for (int c = 0; c < R; ++c)
-      if (straddle[c]) {  // wave-uniform
-#pragma unroll
-        for (int l = 0; l < B; ++l)
-          if (lim[c] < VEC && (lim[c] > 0 || tiny)) xl[l][c] = mask_chunk<S>(xl[l][c], lim[c]);
-      }
-    float p[NV];
-#pragma unroll
-    for (int l = 0; l < B; ++l) {
-      float acc = 0.f;
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(xl[l][c], i), e[c][i], acc);
-      p[l] = acc;
-    }
-    {
-      float acc = 0.f;
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) acc = fmaf(e[c][i], e[c][i], acc);
-      p[B] = acc;
-    }
-#pragma unroll
-    for (int l = 0; l < NV; ++l) {
-      const float v = wave_sum(p[l]);
-      if (lane == 0) red[wave][l] = v;
-    }
-  };
-  auto axpy = [&](const raw (&xl)[B][R], const double (&da)[B]) {
-#pragma unroll
-    for (int l = 0; l < B; ++l) {
-      const float f = (float)da[l];
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) e[c][i] = fmaf(-f, S::get(xl[l][c], i), e[c][i]);
-    }
-    if (ragged) {
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? e[c][i] : 0.f;
-    }
-  };
-
-  if (!pollw) {
-    // ------------------------------------------------------ streaming waves
-    const int64_t wg_row0 = (int64_t)wg * (T * R * VEC);
-    uint32_t boff[R];  // own rows (a chunk with no valid row reads the workgroup's first chunk)
-#pragma unroll
-    for (int c = 0; c < R; ++c)
-      boff[c] = (uint32_t)((lim[c] > 0 ? wg_row0 + (int64_t)VEC * (tid + T * c) : safe_row) * (16 / VEC));
-    uint32_t boffp[R];  // the polling wave's rows, lane for lane (likewise)
-#pragma unroll
-    for (int c = 0; c < R; ++c) {
-      const int64_t r0 = wg_row0 + (int64_t)VEC * (NH * WAVE + lane + T * c);
-      boffp[c] = (uint32_t)((r0 < m ? r0 : safe_row) * (16 / VEC));
-    }
-    raw x0[B][R], x1[B][R], x2[D == 3 ? B : 1][R];
-    raw q0[UPW], q1[UPW], q2[D == 3 ? UPW : 1];  // this wave's share of the poller's rows
-    int bi = (int)(A.blk_begin % nb);
-    const int sw = wave < NH ? wave : 0;  // this streaming wave (bounded for the compiler)
-    // Request block rb: own columns, then chunks u = sw, sw + NH, ... (column
-    // u / R, chunk u % R) of the polling wave's rows.  Loads past the last
-    // column return zero; rows past m are masked before use.
-    auto request = [&](raw (&x)[B][R], raw (&q)[UPW], int rb) {
-      const int j0 = rb * B;
-      const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
-      const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
-      const uint32_t nrec = span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span;
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<char*>(reinterpret_cast<const char*>(A.X) + (int64_t)j0 * col_bytes), 0, (int)nrec, 0x00020000);
-#pragma unroll
-      for (int l = 0; l < B; ++l)
-#pragma unroll
-        for (int c = 0; c < R; ++c)
-          x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
-#pragma unroll
-      for (int i = 0; i < UPW; ++i) {
-        const int u = sw + NH * i;
-        if (i < UMIN || u < U) {  // (the first UMIN are unconditional: the compiler counts them)
-          const int l = u / R, c = u % R;  // wave-uniform
-          uint32_t vo = boffp[0];
-#pragma unroll
-          for (int cc = 1; cc < R; ++cc)
-            if (c == cc) vo = boffp[cc];
-          q[i] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)vo, (int)(l * col_bytes), 0));
-        }
-      }
-    };
-    // (after the block has landed) this wave's share of the poller's rows to LDS
-    auto share = [&](const raw (&q)[UPW]) {
-#pragma unroll
-      for (int i = 0; i < UPW; ++i) {
-        const int u = sw + NH * i;
-        if (i < UMIN || u < U) pbuf[u / R][u % R][lane] = q[i];
-      }
-    };
-    auto ahead = [&](int d) {
-      int r = bi + d;
-      while (r >= nb) r -= nb;
-      return r;
-    };
-    // A step that is not taken (the solve has stopped, or the launch's
-    // blocks are done) still requests its next block: every path to the top
-    // of the loop then issues the same loads in the same order, which keeps
-    // the compiler's own waits for the ring registers exact.  Blocks
-    // requested after the last one used are valid and never read.
-    bool stopped = false;
-    auto step = [&](raw (&cur)[B][R], raw (&q)[UPW], int64_t k) {
-      const int rb = ahead(D);  // the block this buffer holds next
-      if (!stopped && k < nblocks) {
-        // this block (own rows and the share of the poller's rows) has
-        // landed; the next blocks' loads stay in flight
-        wait_vm_at_most<WAIT_N>();
-        share(q);
-        lds_barrier();
-        partials(cur);
-        lds_barrier();
-        // (the polling wave exchanges the partial sums with the grid)
-        lds_barrier();
-        if (__builtin_amdgcn_readfirstlane(sstop)) {
-          stopped = true;
-        } else {
-          double da[B];
-#pragma unroll
-          for (int l = 0; l < B; ++l) da[l] = sda[l];
-          axpy(cur, da);
-          bi = (bi + 1 == nb) ? 0 : bi + 1;
-        }
-      }
-      // the buffer is free: request the block D ahead
-      request(cur, q, rb);
-      pin_order();  // issued early is the point
-    };
-    if (nblocks > 0) {
-      // The loads in flight at the top of the loop are, in issue order,
-      // blocks b .. b+D-1, on entry as on every later turn.
-      pin_order();
-      request(x0, q0, bi);
-      pin_order();
-      request(x1, q1, ahead(1));
-      pin_order();
-      if constexpr (D == 3) {
-        request(x2, q2, ahead(2));
-        pin_order();
-        for (int64_t k = 0;; k += 3) {
-          step(x0, q0, k);
-          step(x1, q1, k + 1);
-          step(x2, q2, k + 2);
-          if (stopped || k + 3 >= nblocks) break;
-        }
-      } else {
-        for (int64_t k = 0;; k += 2) {
-          step(x0, q0, k);
-          step(x1, q1, k + 1);
-          if (stopped || k + 2 >= nblocks) break;
-        }
-      }
-    }
-    // (the loads of the blocks requested past the end are left to land)
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  } else {
-    // --------------------------------------------------------- polling wave
-    // Its vector memory operations (exchange words, coefficients) go ahead of
-    // the streaming waves' queued column loads when both wait to issue.
-    __builtin_amdgcn_s_setprio(3);
-    const bool leader = wg == 0 && lane == 0;  // writes the solve's control words
-    double prev_norm = A.fstat[1];
-    const double ynorm = sqrt(*A.ynorm2);
-    int bi = (int)(A.blk_begin % nb);
-    int sdone = (int)(A.blk_begin / nb);
-    uint32_t seq = (uint32_t)(A.blk_begin + 1);
-    bool aborting = false;
-    Coef<B> c0, c1, c2;
-    // The block coefficients and this workgroup's a_j (columns j = wg + i*P)
-    // are kept in LDS when they fit, so that the step after the exchange
-    // issues no vector memory operation: one issued while the streaming
-    // waves' column loads wait to issue would queue behind them.
-    const int64_t nrdn = (int64_t)nb * B, ncoef = nrdn + (int64_t)nb * NG;
-    const bool coef_lds = ncoef <= MAXCOEF;
-    if (coef_lds) {
-      for (int64_t i = lane; i < nrdn; i += WAVE) scoef[i] = A.rdn[i];
-      for (int64_t i = lane; i < ncoef - nrdn; i += WAVE) scoef[nrdn + i] = A.gram[i];
-    }
-    const int64_t nown = (n - wg + A.P - 1) / A.P;
-    const bool own_lds = nown <= MAXOWN;
-    if (own_lds)
-      for (int64_t i = lane; i < nown; i += WAVE) sown[i] = A.a64[wg + i * A.P];
-    auto load_coef = [&](Coef<B>& cf, int rb) {
-      if (coef_lds) cf.load(scoef, scoef + nrdn, rb, lane);
-      else cf.load(A.rdn, A.gram, rb, lane);
-    };
-    auto finalize = [&](int sd, bool conv, int64_t cols, double nrm2) {
-      if (leader) {
-        A.ctl[CTL_SWEEPS] = sd;
-        A.ctl[CTL_CONVERGED] = conv ? 1 : 0;
-        A.ctl[CTL_DONE] = 1;
-        A.ctl64[C64_COLS] = cols;
-        A.fstat[0] = nrm2;
-      }
-    };
-    // The grid totals of the block, the stop tests, the block's steps da.
-    // True when the solve ends here.
-    auto conclude = [&](const double (&tot)[NV], bool timed_out, const Coef<B>& cf, double (&da)[B]) -> bool {
-      const int j0 = bi * B;
-      if (timed_out) {
-        if (leader) store_flag(&A.ctl[CTL_ERR], ERR_TIMEOUT);
-        return true;
-      }
-      const double nrm2 = tot[B];
-      const double nrm = sqrt(nrm2);
-      if (!(nrm2 <= DBL_MAX)) {
-        if (leader) store_flag(&A.ctl[CTL_ERR], aborting ? ERR_ABORTED : ERR_NONFINITE);
-        finalize(sdone, false, (int64_t)sdone * n + j0, nrm2);
-        return true;
-      }
-      if (bi == 0) {
-        if (leader) { A.hist[sdone] = nrm; A.fstat[1] = nrm; }
-        bool stop = false, conv = false;
-        if (A.stop != STOP_NONE && nrm2 == 0.0) stop = conv = true;
-        else if (A.stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < A.tol * nrm) stop = conv = true;
-        else if (A.stop == STOP_REL_RESID && nrm < A.tol * ynorm) stop = conv = true;
-        if (!stop && sdone >= A.max_sweeps) stop = true;
-        prev_norm = nrm;
-        if (stop) { finalize(sdone, conv, (int64_t)sdone * n, nrm2); return true; }
-      } else if (A.check_cols > 0 && A.stop == STOP_REL_RESID) {
-        const int64_t cols = (int64_t)sdone * n + j0;
-        if (cols % A.check_cols == 0 && (nrm2 == 0.0 || nrm < A.tol * ynorm)) {
-          finalize(sdone, true, cols, nrm2);
-          return true;
-        }
-      }
-      forward_substitute<B>(tot, cf, da);
-      return false;
-    };
-    bool stopped = false;
-    auto step = [&](Coef<B>& ccur, int64_t k) {
-      if (stopped || k >= nblocks) return;
-      lds_barrier();
-      raw xl[B][R];
-#pragma unroll
-      for (int l = 0; l < B; ++l)
-#pragma unroll
-        for (int c = 0; c < R; ++c) xl[l][c] = pbuf[l][c][lane];
-      partials(xl);
-      lds_barrier();
-      const uint64_t* slot_base = A.slots + (int64_t)(seq & 1u) * NV * A.P;
-      bool injected = false;
-      if (lane < NV) {
-        float sacc = 0.f;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) sacc += red[w][lane];
-        // a cancel request rides the norm of a sweep's first block as a NaN
-        if (lane == B && bi == 0 && wg == 0 && load_flag(&A.ctl[CTL_ABORT]) != 0) {
-          sacc = __int_as_float(0x7fc00000);
-          injected = true;
-        }
-        publish(const_cast<uint64_t*>(slot_base) + (int64_t)lane * A.P + wg, seq, sacc);
-      }
-      aborting = __ballot(injected) != 0;
-      if (A.poll_delay) {
-        const uint64_t t0d = now_ticks();
-        while (now_ticks() - t0d < A.poll_delay) __builtin_amdgcn_s_sleep(2);
-      }
-      // chunk c of 64 workgroups: word (l, c*64 + lane); lanes past the last
-      // workgroup read a valid word and count as ready
-      const int ncn = (A.P + WAVE - 1) / WAVE;
-      uint64_t w[NV][MAXC];
-#pragma unroll
-      for (int c = 0; c < MAXC; ++c) {
-        const int idx = c * WAVE + lane;
-        const bool live = c < ncn && idx < A.P;
-#pragma unroll
-        for (int l = 0; l < NV; ++l) w[l][c] = peek(slot_base + (int64_t)l * A.P + (live ? idx : 0));
-      }
-#pragma unroll
-      for (int c = 0; c < MAXC; ++c) {
-        const int idx = c * WAVE + lane;
-        const bool live = c < ncn && idx < A.P;
-#pragma unroll
-        for (int l = 0; l < NV; ++l)
-          if (!live) w[l][c] = (uint64_t)seq << 32;
-      }
-      uint64_t tstart = 0;
-      bool timed_out = false;
-      for (int spin = 0;; ++spin) {
-        bool ready = true;
-#pragma unroll
-        for (int l = 0; l < NV; ++l)
-#pragma unroll
-          for (int c = 0; c < MAXC; ++c) ready = ready && ((uint32_t)(w[l][c] >> 32) == seq);
-        if (ready) break;
-        if (spin == 0) tstart = now_ticks();
-        else if (now_ticks() - tstart > A.timeout_ticks) {
-          timed_out = true;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-        for (int c = 0; c < MAXC; ++c) {
-          const int idx = c * WAVE + lane;
-#pragma unroll
-          for (int l = 0; l < NV; ++l)
-            if ((uint32_t)(w[l][c] >> 32) != seq) w[l][c] = peek(slot_base + (int64_t)l * A.P + idx);
-        }
-      }
-      // fixed order: per lane over its chunks, then across the lanes
-      double tot[NV];
-#pragma unroll
-      for (int l = 0; l < NV; ++l) {
-        double acc = 0.0;
-#pragma unroll
-        for (int c = 0; c < MAXC; ++c) {
-          const int idx = c * WAVE + lane;
-          acc += (c < ncn && idx < A.P) ? (double)__uint_as_float((uint32_t)w[l][c]) : 0.0;
-        }
-        tot[l] = uniform_f64(wave_sum(acc));
-      }
-      double da[B];
-      const bool stop = conclude(tot, __ballot(timed_out) != 0, ccur, da);
-      if (lane == 0) {
-        sstop = stop ? 1 : 0;
-#pragma unroll
-        for (int l = 0; l < B; ++l) sda[l] = da[l];
-      }
-      lds_barrier();
-      if (stop) {
-        stopped = true;
-        return;
-      }
-      axpy(xl, da);
-      // a_j of this block: one lane per column, columns dealt out over the
-      // workgroups
-      if (lane < B) {
-        const int64_t j = (int64_t)bi * B + lane;
-        if (j < n && (int)(j % A.P) == wg) {
-          double d = 0.0;
-#pragma unroll
-          for (int l = 0; l < B; ++l) if (lane == l) d = da[l];
-          if (own_lds) sown[(j - wg) / A.P] += d;
-          else (void)__hip_atomic_fetch_add(&A.a64[j], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
-      int rb = bi + D;
-      while (rb >= nb) rb -= nb;
-      load_coef(ccur, rb);
-      bi = (bi + 1 == nb) ? 0 : bi + 1;
-      if (bi == 0) ++sdone;
-      ++seq;
-    };
-    if (nblocks > 0) {
-      auto at = [&](int d) {
-        int r = bi + d;
-        while (r >= nb) r -= nb;
-        return r;
-      };
-      load_coef(c0, bi);
-      load_coef(c1, at(1));
-      if constexpr (D == 3) {
-        load_coef(c2, at(2));
-        for (int64_t k = 0;; k += 3) {
-          step(c0, k);
-          step(c1, k + 1);
-          step(c2, k + 2);
-          if (stopped || k + 3 >= nblocks) break;
-        }
-      } else {
-        for (int64_t k = 0;; k += 2) {
-          step(c0, k);
-          step(c1, k + 1);
-          if (stopped || k + 2 >= nblocks) break;
-        }
-      }
-    }
-    if (own_lds)
-      for (int64_t i = lane; i < nown; i += WAVE) A.a64[wg + i * A.P] = sown[i];
-  }
-#pragma unroll
-  for (int c = 0; c < R; ++c) {
-    const int64_t r0 = (int64_t)wg * (T * R * VEC) + (int64_t)VEC * (tid + T * c);
-#pragma unroll
-    for (int i = 0; i < VEC; ++i)
-      if (i < lim[c]) A.e_out[r0 + i] = e[c][i];
-  }
 }
 
 // The kernel's SolveArgs read again from the argument segment where they are
@@ -1268,8 +783,24 @@ __device__ inline KArgs cold_args() {
 // order differs), but 16 independent FP64 dot products, one per lane,
 // instead of a serial chain run redundantly by every wave.  Stop logic is
 // that of k_sweep.
-template <class S, int T, int R, int B>
+//
+// Method variants (V):
+//  0  Algorithm 1.
+//  1  Algorithm 2 (Section 7) with blocks of A.thr columns: every column of
+//     such a block steps against the residual at the block's start.  The
+//     kernel keeps a copy es of the residual taken where the current
+//     thr-block began; a column whose thr-block began in an earlier
+//     16-column block takes its dot against es, the others against e, and
+//     the block's step matrix (k_block_inverse16 with thr) removes the steps
+//     of this block that such a column must not see.
+//  2  Column order: sweep s visits the columns A.order[s-1][0..n-1]; block
+//     position p of the sweep is column A.order[s-1][p] (the step matrices of
+//     the sweep's blocks are computed for that order before the sweep).
+// Columns past n in the last block read the block's last valid column
+// again (finite data; their step-matrix rows and columns are zero).
+template <class S, int T, int R, int B, int V>
 __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
+  constexpr bool PAR = V == 1, ORD = V == 2;
   using raw = typename S::raw_t;
   constexpr int VEC = S::VEC;
   constexpr int NW = T / WAVE;
@@ -1299,8 +830,9 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
   // A chunk with no valid row is read at an offset past the block's buffer
   // range, which returns zero and moves no data, when the 32-bit offsets
   // leave room for it (a block spans at most 16 column strides); otherwise
-  // it reads a chunk of valid rows.  Its residual is held at zero either way.
-  const bool oob = 31 * col_bytes < 0xFFFFFFFFll;
+  // (and under a column order, whose buffer range is all of X) it reads a
+  // chunk of valid rows.  Its residual is held at zero either way.
+  const bool oob = !ORD && 31 * col_bytes < 0xFFFFFFFFll;
 #pragma unroll
   for (int c = 0; c < R; ++c) {
     const int64_t r0 = wg_row0 + (int64_t)VEC * (tid + T * c);
@@ -1313,6 +845,15 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
   }
   const bool ragged = wg_end - wg_row0 < (int64_t)(T * R * VEC);
   const bool tiny = m < VEC && !oob;  // no chunk of valid rows to read: every chunk is masked
+  // Algorithm 2: the residual where the current thr-block began
+  float es[PAR ? R : 1][PAR ? VEC : 1];
+  if constexpr (PAR) {
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+#pragma unroll
+      for (int i = 0; i < VEC; ++i) es[c][i] = e[c][i];
+  }
+  const int64_t thr = PAR ? (int64_t)A.thr : 1;
   bool straddle[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) straddle[c] = __ballot(lim[c] < VEC && (lim[c] > 0 || tiny)) != 0;
@@ -1352,19 +893,38 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
         mr[2 * t + 1] = v.y;
       }
     }
-    // the block's columns (loads past the last column return zero)
+    // the block's columns; a column past n reads the last valid one again
+    const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
     raw x[B][R];
+    const int32_t* ordr = nullptr;
+    if constexpr (ORD) {
+      // (the stop test of the last sweep runs on one more block: its loads
+      // reuse the last sweep's order)
+      const int64_t srow = sdone < A.max_sweeps ? sdone : (A.max_sweeps > 0 ? A.max_sweeps - 1 : 0);
+      ordr = A.order + srow * n;
+    }
     {
-      const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
-      const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
-      const uint32_t nrec = span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span;
-      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<char*>(reinterpret_cast<const char*>(A.X) + (int64_t)j0 * col_bytes), 0, (int)nrec, 0x00020000);
+      char* base = const_cast<char*>(reinterpret_cast<const char*>(A.X));
+      uint32_t nrec;
+      if constexpr (ORD) {
+        const int64_t span = n * col_bytes;  // (below 4 GiB: checked by the host)
+        nrec = (uint32_t)span;
+      } else {
+        base += (int64_t)j0 * col_bytes;
+        const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
+        nrec = span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span;
+      }
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)nrec, 0x00020000);
 #pragma unroll
-      for (int l = 0; l < B; ++l)
+      for (int l = 0; l < B; ++l) {
+        const int lc = l < nvalid ? l : nvalid - 1;
+        int coff;
+        if constexpr (ORD) coff = __builtin_amdgcn_readfirstlane((int)((int64_t)ordr[j0 + lc] * col_bytes));
+        else coff = (int)((int64_t)lc * col_bytes);
 #pragma unroll
         for (int c = 0; c < R; ++c)
-          x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
+          x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], coff, 0));
+      }
     }
 #pragma unroll
     for (int c = 0; c < R; ++c)
@@ -1380,10 +940,20 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
 #pragma unroll
       for (int l = 0; l < B; ++l) {
         float acc = 0.f;
+        // Algorithm 2: a column whose thr-block began before this block
+        // takes its dot against the residual saved at that block's start
+        const bool cont = PAR && (j0 + l) / thr * thr < j0;
+        if (cont) {
 #pragma unroll
-        for (int c = 0; c < R; ++c)
+          for (int c = 0; c < R; ++c)
 #pragma unroll
-          for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(x[l][c], i), e[c][i], acc);
+            for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(x[l][c], i), es[PAR ? c : 0][PAR ? i : 0], acc);
+        } else {
+#pragma unroll
+          for (int c = 0; c < R; ++c)
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(x[l][c], i), e[c][i], acc);
+        }
         p[l] = acc;
       }
       float pn = 0.f;
@@ -1527,6 +1097,15 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
     const int fl = __float_as_int((float)dl);
 #pragma unroll
     for (int l = 0; l < B; ++l) {
+      if constexpr (PAR) {
+        // a thr-block begins at this column: keep the residual it starts from
+        if ((j0 + l) % thr == 0 && j0 + l < n) {
+#pragma unroll
+          for (int c = 0; c < R; ++c)
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) es[c][i] = e[c][i];
+        }
+      }
       const float f = __int_as_float(__builtin_amdgcn_readlane(fl, l));
 #pragma unroll
       for (int c = 0; c < R; ++c)
@@ -1540,9 +1119,11 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
         for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? e[c][i] : 0.f;
     }
     if (tid < B) {  // lane tid of wave 0 holds da_tid
-      const int64_t j = j0 + tid;
-      if (j < n && (int)(j % A.P) == wg)
+      const int64_t p = j0 + tid;
+      if (p < n && (int)(p % A.P) == wg) {
+        const int64_t j = ORD ? (int64_t)ordr[p] : p;
         (void)__hip_atomic_fetch_add(&A.a64[j], dl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     bi = (bi + 1 == nb) ? 0 : bi + 1;
     if (bi == 0) ++sdone;
@@ -1555,649 +1136,6 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
     for (int i = 0; i < VEC; ++i)
       if (i < lim[c]) A.e_out[r0 + i] = e[c][i];
   }
-}
-
-// --------------------------------------------------------------------------
-// Warp-specialised grid kernel.  The T data threads own the rows and stream
-// X; one extra wave owns the grid reduction: it sums the data waves' partials,
-// publishes them, and polls the other workgroups' words.  Vector loads of a
-// wave return in issue order, so a wave that both streamed columns and polled
-// would see every poll result only after its outstanding column loads; here
-// the poll wave has nothing else in flight and the data waves request the
-// next blocks as soon as their partials are in LDS.
-template <class S, int T, int R, int B, int D>
-__global__ void __launch_bounds__(T + WAVE) k_sweep_ws(SolveArgs A) {
-  static_assert(D == 2 || D == 3, "prefetch ring of 2 or 3 blocks");
-  using raw = typename S::raw_t;
-  constexpr int VEC = S::VEC;
-  constexpr int NW = T / WAVE;
-  constexpr int NV = B + 1;
-  constexpr int MAXC = 4;                 // up to 256 workgroups
-  constexpr int NTASK = NV * MAXC;        // (value, chunk of 64 workgroups) words per poll lane
-  __shared__ float red[2][NW][NV];
-  __shared__ double tots[2][NV];
-  __shared__ int sflag;
-
-  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
-  const int wg = (int)blockIdx.x;
-  const int64_t m = A.m, n = A.n;
-  const int nb = (int)((n + B - 1) / B);
-  if (A.ctl[CTL_NONFINITE] != 0 || A.ctl[CTL_DONE] != 0) return;
-  if (tid == 0) sflag = 0;
-  const int64_t nblocks = A.blk_end - A.blk_begin;
-  const double ynorm = sqrt(*A.ynorm2);
-
-  auto finalize = [&](int sdone, bool conv, int64_t cols, double nrm2) {
-    if (wg == 0 && tid == 0) {
-      A.ctl[CTL_SWEEPS] = sdone;
-      A.ctl[CTL_CONVERGED] = conv ? 1 : 0;
-      A.ctl[CTL_DONE] = 1;
-      A.ctl64[C64_COLS] = cols;
-      A.fstat[0] = nrm2;
-    }
-  };
-
-  // Block bookkeeping shared by both roles (identical in every thread):
-  // returns true when the solve ends at this block.
-  struct Pos { int bi, sdone; uint32_t seq; double prev_norm; };
-  Pos pos{(int)(A.blk_begin % nb), (int)(A.blk_begin / nb), (uint32_t)(A.blk_begin + 1), A.fstat[1]};
-  auto control = [&](const double (&tot)[NV], bool aborting) -> bool {
-    const int j0 = pos.bi * B;
-    if (sflag) {
-      if (tid == 0) store_flag(&A.ctl[CTL_ERR], ERR_TIMEOUT);
-      return true;
-    }
-    const double nrm2 = tot[B];
-    const double nrm = sqrt(nrm2);
-    if (!(nrm2 <= DBL_MAX)) {
-      if (wg == 0 && tid == 0) store_flag(&A.ctl[CTL_ERR], aborting ? ERR_ABORTED : ERR_NONFINITE);
-      finalize(pos.sdone, false, (int64_t)pos.sdone * n + j0, nrm2);
-      return true;
-    }
-    if (pos.bi == 0) {
-      if (wg == 0 && tid == 0) { A.hist[pos.sdone] = nrm; A.fstat[1] = nrm; }
-      bool stop = false, conv = false;
-      if (A.stop != STOP_NONE && nrm2 == 0.0) stop = conv = true;
-      else if (A.stop == STOP_REL_CHANGE && pos.sdone >= 1 && (pos.prev_norm - nrm) < A.tol * nrm) stop = conv = true;
-      else if (A.stop == STOP_REL_RESID && nrm < A.tol * ynorm) stop = conv = true;
-      if (!stop && pos.sdone >= A.max_sweeps) stop = true;
-      pos.prev_norm = nrm;
-      if (stop) { finalize(pos.sdone, conv, (int64_t)pos.sdone * n, nrm2); return true; }
-    } else if (A.check_cols > 0 && A.stop == STOP_REL_RESID) {
-      const int64_t cols = (int64_t)pos.sdone * n + j0;
-      if (cols % A.check_cols == 0 && (nrm2 == 0.0 || nrm < A.tol * ynorm)) {
-        finalize(pos.sdone, true, cols, nrm2);
-        return true;
-      }
-    }
-    return false;
-  };
-  auto advance = [&]() {
-    pos.bi = pos.bi + 1 == nb ? 0 : pos.bi + 1;
-    if (pos.bi == 0) ++pos.sdone;
-    ++pos.seq;
-  };
-
-  if (tid >= T) {
-    // ---------------- reduction wave: publish, poll, hand the totals over
-    __syncthreads();  // matches the data waves' prologue barrier
-    const int ncn = (A.P + WAVE - 1) / WAVE;
-    for (int64_t k = 0; k < nblocks; ++k) {
-      const int par = (int)(pos.seq & 1u);
-      const uint32_t seq = pos.seq;
-      __syncthreads();  // data waves' partials are in LDS
-      uint64_t* slot_base = A.slots + (int64_t)par * NV * A.P;
-      if (lane < NV) {
-        float sacc = 0.f;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) sacc += red[par][w][lane];
-        publish(slot_base + (int64_t)lane * A.P + wg, seq, sacc);
-      }
-      __syncthreads();  // published: the data waves may now request columns
-      uint64_t w[NTASK];
-#pragma unroll
-      for (int t = 0; t < NTASK; ++t) {
-        const int l = t / MAXC, c = t % MAXC, idx = c * WAVE + lane;
-        const bool live = c < ncn && idx < A.P;
-        w[t] = live ? peek(slot_base + (int64_t)l * A.P + idx) : ((uint64_t)seq << 32);
-      }
-      uint64_t tstart = 0;
-      bool timed_out = false;
-      for (int spin = 0;; ++spin) {
-        bool ready = true;
-#pragma unroll
-        for (int t = 0; t < NTASK; ++t) ready = ready && ((uint32_t)(w[t] >> 32) == seq);
-        if (ready) break;
-        if (spin == 0) tstart = now_ticks();
-        else if (now_ticks() - tstart > A.timeout_ticks) {
-          timed_out = true;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-        for (int t = 0; t < NTASK; ++t) {
-          if ((uint32_t)(w[t] >> 32) != seq) {
-            const int l = t / MAXC, c = t % MAXC, idx = c * WAVE + lane;
-            w[t] = peek(slot_base + (int64_t)l * A.P + idx);
-          }
-        }
-      }
-#pragma unroll
-      for (int l = 0; l < NV; ++l) {
-        double acc = 0.0;
-#pragma unroll
-        for (int c = 0; c < MAXC; ++c) {
-          const int idx = c * WAVE + lane;
-          const bool live = c < ncn && idx < A.P;
-          acc += live ? (double)__uint_as_float((uint32_t)w[l * MAXC + c]) : 0.0;
-        }
-        const double tl = wave_sum(acc);
-        if (lane == 0) tots[par][l] = tl;
-      }
-      if (timed_out && lane == 0) sflag = 1;
-      __syncthreads();  // totals are in LDS
-      double tot[NV];
-#pragma unroll
-      for (int l = 0; l < NV; ++l) tot[l] = uniform_f64(tots[par][l]);
-      if (control(tot, false)) break;
-      advance();
-    }
-    return;
-  }
-
-  // ---------------- data waves: rows of the residual, column stream
-  float e[R][VEC];
-  int lim[R];
-  int64_t rof[R];
-  uint32_t boff[R];
-#pragma unroll
-  for (int c = 0; c < R; ++c) {
-    rof[c] = (int64_t)wg * (T * R * VEC) + (int64_t)VEC * (tid + T * c);
-    const int64_t left = m - rof[c];
-    lim[c] = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
-    boff[c] = (uint32_t)(rof[c] * (16 / VEC));
-#pragma unroll
-    for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? A.e0[rof[c] + i] : 0.f;
-  }
-  const int64_t col_bytes = A.ldx * (int64_t)(16 / VEC);
-  raw x0[B][R], x1[B][R], x2[D == 3 ? B : 1][R];
-  Coef<B> c0, c1, c2;
-
-  auto load_block = [&](raw (&x)[B][R], Coef<B>& cf, int bi) {
-    bi = __builtin_amdgcn_readfirstlane(bi);  // (uniform: keeps the resource in scalar registers)
-    const int j0 = bi * B;
-    const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
-    const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
-    const uint32_t nrec = span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span;
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<char*>(reinterpret_cast<const char*>(A.X) + (int64_t)j0 * col_bytes), 0, (int)nrec, 0x00020000);
-#pragma unroll
-    for (int l = 0; l < B; ++l) {
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        if (lim[c] > 0)
-          x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
-        else
-          x[l][c] = S::zero();
-      }
-    }
-    cf.load(A.rdn, A.gram, bi, lane);
-  };
-
-  auto step = [&](raw (&cur)[B][R], auto& pf, Coef<B>& ccur, Coef<B>& cpf, bool has_next) -> bool {
-    const int j0 = pos.bi * B;
-    int pbi = pos.bi + D - 1;
-    while (pbi >= nb) pbi -= nb;
-    const int par = (int)(pos.seq & 1u);
-    float p[NV];
-#pragma unroll
-    for (int l = 0; l < B; ++l) {
-      float acc = 0.f;
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        if (lim[c] < VEC) cur[l][c] = mask_chunk<S>(cur[l][c], lim[c]);
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(cur[l][c], i), e[c][i], acc);
-      }
-      p[l] = acc;
-    }
-    {
-      float acc = 0.f;
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) acc = fmaf(e[c][i], e[c][i], acc);
-      p[B] = acc;
-    }
-    bool aborting = false;
-    if (pos.bi == 0 && wg == 0 && tid == 0 && load_flag(&A.ctl[CTL_ABORT]) != 0) {
-      p[B] = __int_as_float(0x7fc00000);
-      aborting = true;
-    }
-#pragma unroll
-    for (int l = 0; l < NV; ++l) {
-      const float v = wave_sum(p[l]);
-      if (lane == 0) red[par][wave][l] = v;
-    }
-    __syncthreads();  // partials to the reduction wave
-    __syncthreads();  // the reduction wave has published (its stores precede our loads)
-    if (has_next) load_block(pf, cpf, pbi);
-    __syncthreads();  // totals from the reduction wave
-    double tot[NV];
-#pragma unroll
-    for (int l = 0; l < NV; ++l) tot[l] = uniform_f64(tots[par][l]);
-    if (control(tot, aborting)) return true;
-    double da[B];
-    forward_substitute<B>(tot, ccur, da);
-#pragma unroll
-    for (int l = 0; l < B; ++l) {
-      const float f = (float)da[l];
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) e[c][i] = fmaf(-f, S::get(cur[l][c], i), e[c][i]);
-    }
-    if (tid < B) {
-      const int64_t j = j0 + tid;
-      if (j < n && (int)(j % A.P) == wg) {
-        double d = 0.0;
-#pragma unroll
-        for (int l = 0; l < B; ++l) if (tid == l) d = da[l];
-        (void)__hip_atomic_fetch_add(&A.a64[j], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
-    advance();
-    return false;
-  };
-
-  if (nblocks > 0) load_block(x0, c0, pos.bi);
-  if constexpr (D == 3) {
-    if (nblocks > 1) load_block(x1, c1, pos.bi + 1 == nb ? 0 : pos.bi + 1);
-  }
-  __syncthreads();
-  for (int64_t k = 0; k < nblocks;) {
-    if constexpr (D == 2) {
-      if (step(x0, x1, c0, c1, k + 1 < nblocks)) break;
-      if (++k >= nblocks) break;
-      if (step(x1, x0, c1, c0, k + 1 < nblocks)) break;
-      ++k;
-    } else {
-      if (step(x0, x2, c0, c2, k + 2 < nblocks)) break;
-      if (++k >= nblocks) break;
-      if (step(x1, x0, c1, c0, k + 2 < nblocks)) break;
-      if (++k >= nblocks) break;
-      if (step(x2, x1, c2, c1, k + 2 < nblocks)) break;
-      ++k;
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < R; ++c)
-#pragma unroll
-    for (int i = 0; i < VEC; ++i)
-      if (i < lim[c]) A.e_out[rof[c] + i] = e[c][i];
-}
-
-// --------------------------------------------------------------------------
-// Pipelined grid kernel: two reductions in flight.
-//
-// Let E_k be the residual after the updates of blocks < k.  Step k publishes
-// the dots of block k against the residual it holds, which still lacks block
-// k-1's update (E_{k-1}), and only then waits for the reduction of block k-1
-// (published one step earlier).  Block k-1's true dots follow exactly from
-//     <X_l, E_{k-1}> = h_l - sum_i <X_l, X_{k-2,i}> da_{k-2,i}
-// (the Gram entries between consecutive blocks, computed once), after which
-// its in-block forward substitution and axpy run as in k_sweep.  Every
-// iterate is the one Algorithm 1 produces; the reduction latency is spread
-// over two steps.  The first block of every sweep is handled without lag
-// (the pipeline is drained), so the sweep-end norm and the stop test use the
-// exact residual.  Ring of four register buffers: block k-1 (axpy pending),
-// block k (dots), block k+1 (landed), block k+2 (requested at step k).
-template <int B>
-struct CoefX {
-  static constexpr int NG = B * (B - 1) / 2;
-  static constexpr int NX = B * B;
-  static constexpr int NT = B + NG + NX;
-  static constexpr int NCR = (NT + WAVE - 1) / WAVE;
-  double v[NCR];
-  __device__ inline void load(const double* rdn, const double* gram, const double* cross, int64_t bi, int lane) {
-#pragma unroll
-    for (int r = 0; r < NCR; ++r) {
-      const int q = r * WAVE + lane;
-      double x = 0.0;
-      if (q < B) x = rdn[bi * B + q];
-      else if (q < B + NG) x = gram[bi * NG + (q - B)];
-      else if (q < NT) x = cross[bi * NX + (q - B - NG)];
-      v[r] = x;
-    }
-  }
-  __device__ inline double get(int q) const { return readlane_f64(v[q / WAVE], q % WAVE); }
-};
-
-template <class S, int T, int R, int B>
-__global__ void __launch_bounds__(T) k_sweep_pipe(SolveArgs A) {
-  using raw = typename S::raw_t;
-  using CF = CoefX<B>;
-  constexpr int VEC = S::VEC;
-  constexpr int NW = T / WAVE;
-  constexpr int NV = B + 1;
-  constexpr int MAXC = 8;
-  constexpr int MAXT = (NV * MAXC + NW - 1) / NW < 8 ? (NV * MAXC + NW - 1) / NW : 8;
-  __shared__ float red[2][NW][NV];
-  __shared__ double gsum[2][NV][MAXC];
-  __shared__ int sflag;
-
-  const int tid = threadIdx.x, lane = tid & (WAVE - 1), wave = tid / WAVE;
-  const int wg = (int)blockIdx.x;
-  const int64_t m = A.m, n = A.n;
-  const int nb = (int)((n + B - 1) / B);
-  if (A.ctl[CTL_NONFINITE] != 0 || A.ctl[CTL_DONE] != 0) return;
-  if (tid == 0) sflag = 0;
-
-  float e[R][VEC];
-  int lim[R];
-  int64_t rof[R];
-  uint32_t boff[R];
-#pragma unroll
-  for (int c = 0; c < R; ++c) {
-    rof[c] = (int64_t)wg * (T * R * VEC) + (int64_t)VEC * (tid + T * c);
-    const int64_t left = m - rof[c];
-    lim[c] = left <= 0 ? 0 : (left >= VEC ? VEC : (int)left);
-    boff[c] = (uint32_t)(rof[c] * (16 / VEC));
-#pragma unroll
-    for (int i = 0; i < VEC; ++i) e[c][i] = (i < lim[c]) ? A.e0[rof[c] + i] : 0.f;
-  }
-  double prev_norm = A.fstat[1];
-  const double ynorm = sqrt(*A.ynorm2);
-  const int64_t nblocks = A.blk_end - A.blk_begin;
-  const int64_t col_bytes = A.ldx * (int64_t)(16 / VEC);
-
-  raw x0[B][R], x1[B][R], x2[B][R], x3[B][R];
-  CF c0, c1, c2, c3;
-
-  auto load_block = [&](raw (&x)[B][R], CF& cf, int bi) {
-    bi = __builtin_amdgcn_readfirstlane(bi);  // (uniform: keeps the resource in scalar registers)
-    const int j0 = bi * B;
-    const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
-    const int64_t span = (int64_t)(nvalid - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
-    const uint32_t nrec = span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span;
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<char*>(reinterpret_cast<const char*>(A.X) + (int64_t)j0 * col_bytes), 0, (int)nrec, 0x00020000);
-#pragma unroll
-    for (int l = 0; l < B; ++l) {
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        if (lim[c] > 0)
-          x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
-        else
-          x[l][c] = S::zero();
-      }
-    }
-    cf.load(A.rdn, A.gram, A.cross, bi, lane);
-  };
-
-  auto finalize = [&](int sdone, bool conv, int64_t cols, double nrm2) {
-    if (wg == 0 && tid == 0) {
-      A.ctl[CTL_SWEEPS] = sdone;
-      A.ctl[CTL_CONVERGED] = conv ? 1 : 0;
-      A.ctl[CTL_DONE] = 1;
-      A.ctl64[C64_COLS] = cols;
-      A.fstat[0] = nrm2;
-    }
-  };
-
-  // Grid reduction of exchange `sq` (published by every workgroup) into tot.
-  // Returns false on timeout.
-  auto poll = [&](uint32_t sq, double (&tot)[NV]) -> bool {
-    const int par = (int)(sq & 1u);
-    const uint64_t* slot_base = A.slots + (int64_t)(sq & 3u) * NV * A.P;
-    const int ncn = (A.P + WAVE - 1) / WAVE;
-    const int ntask = NV * ncn;
-    bool timed_out = false;
-    for (int t0 = wave; t0 < ntask; t0 += NW * MAXT) {
-      uint64_t w[MAXT];
-#pragma unroll
-      for (int q = 0; q < MAXT; ++q) {
-        const int t = t0 + q * NW;
-        const int l = t / ncn, c = t - l * ncn, idx = c * WAVE + lane;
-        const bool live = t < ntask && idx < A.P;
-        w[q] = live ? peek(slot_base + (int64_t)l * A.P + idx) : ((uint64_t)sq << 32);
-      }
-      uint64_t tstart = 0;
-      for (int spin = 0;; ++spin) {
-        bool ready = true;
-#pragma unroll
-        for (int q = 0; q < MAXT; ++q) ready = ready && ((uint32_t)(w[q] >> 32) == sq);
-        if (ready) break;
-        if (spin == 0) tstart = now_ticks();
-        else if (now_ticks() - tstart > A.timeout_ticks) {
-          timed_out = true;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-#pragma unroll
-        for (int q = 0; q < MAXT; ++q) {
-          if ((uint32_t)(w[q] >> 32) != sq) {
-            const int t = t0 + q * NW;
-            const int l = t / ncn, c = t - l * ncn, idx = c * WAVE + lane;
-            w[q] = peek(slot_base + (int64_t)l * A.P + idx);
-          }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < MAXT; ++q) {
-        const int t = t0 + q * NW;
-        if (t < ntask) {
-          const int l = t / ncn, c = t - l * ncn, idx = c * WAVE + lane;
-          const double v = wave_sum(idx < A.P ? (double)__uint_as_float((uint32_t)w[q]) : 0.0);
-          if (lane == 0) gsum[par][l][c] = v;
-        }
-      }
-    }
-    if (timed_out) sflag = 1;
-    __syncthreads();
-    if (sflag) {
-      if (tid == 0) store_flag(&A.ctl[CTL_ERR], ERR_TIMEOUT);
-      return false;
-    }
-#pragma unroll
-    for (int l = 0; l < NV; ++l) {
-      double sacc = 0.0;
-      for (int c = 0; c < ncn; ++c) sacc += gsum[par][l][c];
-      tot[l] = uniform_f64(sacc);
-    }
-    return true;
-  };
-
-  // In-block forward substitution, optionally after removing the part of the
-  // dots due to the previous block's not yet applied update.
-  auto solve_block = [&](const double (&tot)[NV], const CF& cf, bool lagged, const double (&dprev)[B],
-                         double (&da)[B]) {
-    double g[B];
-#pragma unroll
-    for (int l = 0; l < B; ++l) {
-      double acc = tot[l];
-      if (lagged) {
-#pragma unroll
-        for (int i = 0; i < B; ++i) acc -= cf.get(B + CF::NG + l * B + i) * dprev[i];
-      }
-      g[l] = acc;
-    }
-#pragma unroll
-    for (int l = 0; l < B; ++l) {
-      double acc = g[l];
-#pragma unroll
-      for (int i = 0; i < l; ++i) acc -= cf.get(B + l * (l - 1) / 2 + i) * da[i];
-      da[l] = uniform_f64(acc * cf.get(l));
-    }
-  };
-
-  auto apply = [&](const raw (&x)[B][R], const double (&da)[B], int j0) {
-#pragma unroll
-    for (int l = 0; l < B; ++l) {
-      const float f = (float)da[l];
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) e[c][i] = fmaf(-f, S::get(x[l][c], i), e[c][i]);
-    }
-    if (tid < B) {
-      const int64_t j = j0 + tid;
-      if (j < n && (int)(j % A.P) == wg) {
-        double d = 0.0;
-#pragma unroll
-        for (int l = 0; l < B; ++l) if (tid == l) d = da[l];
-        (void)__hip_atomic_fetch_add(&A.a64[j], d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
-  };
-
-  int bi = (int)(A.blk_begin % nb);
-  int sdone = (int)(A.blk_begin / nb);
-  uint32_t seq = (uint32_t)(A.blk_begin + 1);
-  // pipeline state: the pending (published, not yet applied) block
-  bool pending = false, pend_lag = false;
-  int pend_bi = 0;
-  double dprev[B];  // da of the block before the pending one
-#pragma unroll
-  for (int l = 0; l < B; ++l) dprev[l] = 0.0;
-
-  // Wait for the pending block's reduction and apply its update.
-  auto retire = [&](const raw (&xp)[B][R], const CF& cp) -> bool {
-    double tot[NV];
-    if (!poll(seq - 1, tot)) return false;
-    if (!(tot[B] <= DBL_MAX)) {
-      if (wg == 0 && tid == 0) store_flag(&A.ctl[CTL_ERR], ERR_NONFINITE);
-      finalize(sdone, false, (int64_t)sdone * n + (int64_t)pend_bi * B, tot[B]);
-      return false;
-    }
-    double da[B];
-    solve_block(tot, cp, pend_lag, dprev, da);
-    apply(xp, da, pend_bi * B);
-#pragma unroll
-    for (int l = 0; l < B; ++l) dprev[l] = da[l];
-    pending = false;
-    return true;
-  };
-
-  // One step; returns true when the kernel must stop.
-  auto step = [&](raw (&prv)[B][R], raw (&cur)[B][R], raw (&pf)[B][R], CF& cprv, CF& ccur, CF& cpf,
-                  bool has_pf) -> bool {
-    const int j0 = bi * B;
-    int pbi = bi + 2;
-    while (pbi >= nb) pbi -= nb;
-    if (bi == 0 && pending) {
-      if (!retire(prv, cprv)) return true;
-    }
-    float p[NV];
-#pragma unroll
-    for (int l = 0; l < B; ++l) {
-      float acc = 0.f;
-#pragma unroll
-      for (int c = 0; c < R; ++c) {
-        if (lim[c] < VEC) cur[l][c] = mask_chunk<S>(cur[l][c], lim[c]);
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(cur[l][c], i), e[c][i], acc);
-      }
-      p[l] = acc;
-    }
-    {
-      float acc = 0.f;
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) acc = fmaf(e[c][i], e[c][i], acc);
-      p[B] = acc;
-    }
-    bool aborting = false;
-    if (bi == 0 && wg == 0 && tid == 0 && load_flag(&A.ctl[CTL_ABORT]) != 0) {
-      p[B] = __int_as_float(0x7fc00000);
-      aborting = true;
-    }
-    const int rpar = (int)(seq & 1u);
-#pragma unroll
-    for (int l = 0; l < NV; ++l) {
-      const float v = wave_sum(p[l]);
-      if (lane == 0) red[rpar][wave][l] = v;
-    }
-    __syncthreads();
-    if (tid < NV) {
-      float sacc = 0.f;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) sacc += red[rpar][w][tid];
-      publish(A.slots + (int64_t)(seq & 3u) * NV * A.P + (int64_t)tid * A.P + wg, seq, sacc);
-    }
-    const bool lag_now = pending;  // the dots just published lack the pending block's update
-
-    if (bi == 0) {
-      // Synchronous step at a sweep boundary: exact residual, exact norm.
-      double tot[NV];
-      if (!poll(seq, tot)) return true;
-      if (has_pf) load_block(pf, cpf, pbi);
-      const double nrm2 = tot[B], nrm = sqrt(nrm2);
-      if (!(nrm2 <= DBL_MAX)) {
-        if (wg == 0 && tid == 0) store_flag(&A.ctl[CTL_ERR], aborting ? ERR_ABORTED : ERR_NONFINITE);
-        finalize(sdone, false, (int64_t)sdone * n, nrm2);
-        return true;
-      }
-      if (wg == 0 && tid == 0) { A.hist[sdone] = nrm; A.fstat[1] = nrm; }
-      bool stop = false, conv = false;
-      if (A.stop != STOP_NONE && nrm2 == 0.0) stop = conv = true;
-      else if (A.stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < A.tol * nrm) stop = conv = true;
-      else if (A.stop == STOP_REL_RESID && nrm < A.tol * ynorm) stop = conv = true;
-      if (!stop && sdone >= A.max_sweeps) stop = true;
-      prev_norm = nrm;
-      if (stop) { finalize(sdone, conv, (int64_t)sdone * n, nrm2); return true; }
-      double da[B];
-      const double zero[B] = {};
-      solve_block(tot, ccur, false, zero, da);
-      apply(cur, da, j0);
-#pragma unroll
-      for (int l = 0; l < B; ++l) dprev[l] = da[l];
-      pending = false;
-    } else {
-      if (pending) {
-        if (!retire(prv, cprv)) return true;
-      }
-      if (has_pf) load_block(pf, cpf, pbi);
-      pending = true;
-      pend_lag = lag_now;
-      pend_bi = bi;
-    }
-    bi = bi + 1 == nb ? 0 : bi + 1;
-    if (bi == 0) ++sdone;
-    ++seq;
-    return false;
-  };
-
-  if (nblocks > 0) load_block(x0, c0, bi);
-  if (nblocks > 1) load_block(x1, c1, bi + 1 == nb ? 0 : bi + 1);
-  __syncthreads();
-  int64_t k = 0;
-  bool stopped = false;
-  while (k < nblocks) {
-    if (step(x3, x0, x2, c3, c0, c2, k + 2 < nblocks)) { stopped = true; break; }
-    if (++k >= nblocks) break;
-    if (step(x0, x1, x3, c0, c1, c3, k + 2 < nblocks)) { stopped = true; break; }
-    if (++k >= nblocks) break;
-    if (step(x1, x2, x0, c1, c2, c0, k + 2 < nblocks)) { stopped = true; break; }
-    if (++k >= nblocks) break;
-    if (step(x2, x3, x1, c2, c3, c1, k + 2 < nblocks)) { stopped = true; break; }
-    ++k;
-  }
-  // A launch that ends inside a sweep retires its last block before exiting.
-  if (!stopped && pending) {
-    switch ((int)((k - 1) & 3)) {
-      case 0: retire(x0, c0); break;
-      case 1: retire(x1, c1); break;
-      case 2: retire(x2, c2); break;
-      default: retire(x3, c3); break;
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < R; ++c)
-#pragma unroll
-    for (int i = 0; i < VEC; ++i)
-      if (i < lim[c]) A.e_out[rof[c] + i] = e[c][i];
 }
 
 // --------------------------------------------------------------------------
@@ -2411,77 +1349,62 @@ __global__ void __launch_bounds__(BShape<W>::T) k_batched(BatchArgs A) {
   X_(F32, 256, 2, 8, false, 3) X_(F32, 256, 2, 8, false, 4) X_(F32, 256, 2, 4, false, 4)       \
   X_(BF16, 256, 1, 8, false, 3) X_(BF16, 256, 1, 8, false, 4) X_(BF16, 256, 1, 4, false, 4)
 
-#define HPSCD_PIPE_VARIANTS(X_)                                                   \
-  X_(F32, 1024, 1, 2) X_(F32, 512, 2, 2) X_(F32, 512, 2, 4) X_(F32, 256, 4, 4)    \
-  X_(F32, 256, 1, 4) X_(F32, 256, 2, 4)                                             \
-  X_(BF16, 512, 1, 4) X_(BF16, 256, 2, 4)
-
-#define HPSCD_WS_VARIANTS(X_)                                                                     \
-  X_(F32, 512, 2, 4, 3) X_(F32, 512, 2, 8, 2) X_(F32, 512, 2, 4, 2) X_(F32, 256, 4, 4, 3)          \
-  X_(F32, 256, 4, 8, 2) X_(F32, 256, 4, 8, 3) X_(F32, 1024, 1, 4, 2) X_(F32, 1024, 1, 2, 2)        \
-  X_(F32, 1024, 1, 4, 3) X_(F32, 256, 1, 4, 2) X_(F32, 256, 1, 8, 2)                              \
-  X_(BF16, 512, 1, 8, 2) X_(BF16, 512, 1, 4, 3) X_(BF16, 512, 1, 8, 3) X_(BF16, 256, 2, 8, 3)
-
 #define HPSCD_IS_BF16_F32 false
 #define HPSCD_IS_BF16_BF16 true
 
 struct Variant {
   int T, R, B;
   bool bf16, grid;
-  int D;           // 2, 3: prefetch ring; 4: pipelined; 12, 13: warp-specialised with ring 2, 3
+  int D;           // 2, 3, 4: prefetch ring (k_sweep); 5: polling waves (k_sweep_px); 8: wide blocks
   const void* fn;
   int threads;     // launch width
+  int V;           // method variant of the wide-block kernel (0: Algorithm 1)
 };
 
 #define HPSCD_ENTRY(S, T, R, B, G, D) \
-  {T, R, B, HPSCD_IS_BF16_##S, G, D, reinterpret_cast<const void*>(&k_sweep<S, T, R, B, G, D>), T},
-#define HPSCD_WENTRY(S, T, R, B, D) \
-  {T, R, B, HPSCD_IS_BF16_##S, true, 10 + D, reinterpret_cast<const void*>(&k_sweep_ws<S, T, R, B, D>), T + WAVE},
-#define HPSCD_PENTRY(S, T, R, B) \
-  {T, R, B, HPSCD_IS_BF16_##S, true, 4, reinterpret_cast<const void*>(&k_sweep_pipe<S, T, R, B>), T},
+  {T, R, B, HPSCD_IS_BF16_##S, G, D, reinterpret_cast<const void*>(&k_sweep<S, T, R, B, G, D>), T, 0},
 #define HPSCD_PX_VARIANTS(X_) \
   X_(F32, 512, 2, 8, 2) X_(F32, 512, 2, 4, 1) X_(F32, 256, 4, 4, 1) X_(F32, 256, 4, 8, 2) X_(BF16, 512, 1, 8, 2)
 #define HPSCD_XENTRY(S, T, R, B, NPW) \
-  {T, R, B, HPSCD_IS_BF16_##S, true, 5, reinterpret_cast<const void*>(&k_sweep_px<S, T, R, B, NPW>), T},
-#define HPSCD_PE_VARIANTS(X_)                                                                               \
-  X_(F32, 512, 2, 8, 2) X_(F32, 512, 2, 8, 3) X_(F32, 1024, 1, 8, 2) X_(F32, 512, 2, 4, 2) X_(F32, 512, 2, 4, 3) \
-  X_(BF16, 512, 1, 8, 2) X_(BF16, 512, 1, 8, 3)
-// kind 6: ring of 2 blocks; kind 7: ring of 3
-#define HPSCD_EENTRY(S, T, R, B, D) \
-  {T, R, B, HPSCD_IS_BF16_##S, true, 4 + D, reinterpret_cast<const void*>(&k_sweep_pe<S, T, R, B, D>), T},
+  {T, R, B, HPSCD_IS_BF16_##S, true, 5, reinterpret_cast<const void*>(&k_sweep_px<S, T, R, B, NPW>), T, 0},
 // kind 8: wide blocks, no prefetch
 #define HPSCD_WIDE_VARIANTS(X_) X_(F32, 512, 2, 16) X_(BF16, 512, 1, 16) X_(F32, 256, 4, 16) X_(F32, 1024, 1, 16) \
   X_(F32, 512, 1, 16) X_(F32, 256, 1, 16)
 #define HPSCD_WBENTRY(S, T, R, B) \
-  {T, R, B, HPSCD_IS_BF16_##S, true, 8, reinterpret_cast<const void*>(&k_sweep_wide<S, T, R, B>), T},
+  {T, R, B, HPSCD_IS_BF16_##S, true, 8, reinterpret_cast<const void*>(&k_sweep_wide<S, T, R, B, 0>), T, 0},
 #define HPSCD_WB1ENTRY(S, T, R, B) \
-  {T, R, B, HPSCD_IS_BF16_##S, false, 8, reinterpret_cast<const void*>(&k_sweep_wide<S, T, R, B>), T},
-static const Variant kVariants[] = {HPSCD_SWEEP_VARIANTS(HPSCD_ENTRY) HPSCD_PIPE_VARIANTS(HPSCD_PENTRY)
-                                        HPSCD_WS_VARIANTS(HPSCD_WENTRY) HPSCD_PX_VARIANTS(HPSCD_XENTRY)
-                                            HPSCD_PE_VARIANTS(HPSCD_EENTRY) HPSCD_WIDE_VARIANTS(HPSCD_WBENTRY)
-                                            HPSCD_WIDE_VARIANTS(HPSCD_WB1ENTRY)};
+  {T, R, B, HPSCD_IS_BF16_##S, false, 8, reinterpret_cast<const void*>(&k_sweep_wide<S, T, R, B, 0>), T, 0},
+// the method variants (Algorithm 2, column order) of the FP32 shapes
+#define HPSCD_WIDE_F32_VARIANTS(X_) X_(512, 2, 1) X_(256, 4, 1) X_(1024, 1, 1) X_(512, 1, 1) X_(256, 1, 1) \
+  X_(512, 2, 2) X_(256, 4, 2) X_(1024, 1, 2) X_(512, 1, 2) X_(256, 1, 2)
+#define HPSCD_WVENTRY(T, R, V) \
+  {T, R, 16, false, true, 8, reinterpret_cast<const void*>(&k_sweep_wide<F32, T, R, 16, V>), T, V}, \
+  {T, R, 16, false, false, 8, reinterpret_cast<const void*>(&k_sweep_wide<F32, T, R, 16, V>), T, V},
+static const Variant kVariants[] = {HPSCD_SWEEP_VARIANTS(HPSCD_ENTRY) HPSCD_PX_VARIANTS(HPSCD_XENTRY)
+                                        HPSCD_WIDE_VARIANTS(HPSCD_WBENTRY) HPSCD_WIDE_VARIANTS(HPSCD_WB1ENTRY)
+                                            HPSCD_WIDE_F32_VARIANTS(HPSCD_WVENTRY)};
 
 // The deepest prefetch ring built for the shape (D = 0: any).
-static const Variant* find_variant(int T, int R, int B, bool bf16, bool grid, int D = 0) {
+static const Variant* find_variant(int T, int R, int B, bool bf16, bool grid, int D = 0, int V = 0) {
   const Variant* best = nullptr;
   for (const Variant& v : kVariants)
-    if (v.T == T && v.R == R && v.B == B && v.bf16 == bf16 && v.grid == grid && (D == 0 || v.D == D))
+    if (v.T == T && v.R == R && v.B == B && v.bf16 == bf16 && v.grid == grid && (D == 0 || v.D == D) && v.V == V)
       if (!best || v.D > best->D) best = &v;
   return best;
 }
 
-bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid, int D) {
-  return find_variant(T, R, B, bf16, grid, D) != nullptr;
+bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid, int D, int V) {
+  return find_variant(T, R, B, bf16, grid, D, V) != nullptr;
 }
 
-int sweep_max_workgroups(int T, int R, int B, bool bf16, bool grid, int D) {
-  const Variant* v = find_variant(T, R, B, bf16, grid, D);
+int sweep_max_workgroups(int T, int R, int B, bool bf16, bool grid, int D, int V) {
+  const Variant* v = find_variant(T, R, B, bf16, grid, D, V);
   if (!v) return 0;
-  return (v->D >= 10 || (v->D >= 5 && v->D <= 8)) ? 256 : 512;
+  return v->D >= 5 ? 256 : 512;
 }
 
-int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid, int D) {
-  const Variant* v = find_variant(T, R, B, bf16, grid, D);
+int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid, int D, int V) {
+  const Variant* v = find_variant(T, R, B, bf16, grid, D, V);
   if (!v) return 0;
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn, v->threads, 0) != hipSuccess) return 0;
@@ -2489,8 +1412,8 @@ int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid, int D) {
 }
 
 hipError_t launch_sweep(int T, int R, int B, bool bf16, bool grid, int D, const SolveArgs& a, hipStream_t s,
-                        bool cooperative) {
-  const Variant* v = find_variant(T, R, B, bf16, grid, D);
+                        bool cooperative, int V) {
+  const Variant* v = find_variant(T, R, B, bf16, grid, D, V);
   if (!v) return hipErrorInvalidValue;
   SolveArgs args = a;
   void* kargs[] = {&args};

@@ -9,8 +9,10 @@ Layout: a system's X is passed as a torch tensor ``Xt`` of shape ``(n, ldx)``
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -40,7 +42,7 @@ def hip_runtimes_mapped():
 if len(hip_runtimes_mapped()) != 1:
     raise ImportError(f"expected one HIP runtime in the process, found {hip_runtimes_mapped()}")
 
-STOP_NONE, STOP_REL_CHANGE, STOP_REL_RESID = 0, 1, 2
+STOP_NONE, STOP_REL_CHANGE, STOP_REL_RESID, STOP_REL_GRAD = 0, 1, 2, 3
 F_NO_FINAL_CHECK, F_FORCE_GRID, F_FORCE_WG, F_NO_COOP = 1, 2, 4, 8
 
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EABORTED, ETIMEOUT = range(7)
@@ -50,7 +52,8 @@ _NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENONFINITE", 5: "
 class Opts(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int32), ("stop", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("check_cols", ctypes.c_int64), ("refresh_cols", ctypes.c_int64), ("block", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("team_threads", ctypes.c_int32), ("depth", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("team_threads", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("thr", ctypes.c_int32), ("order", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -59,7 +62,7 @@ class Info(ctypes.Structure):
                 ("final_rel_resid", ctypes.c_double), ("y_norm", ctypes.c_double),
                 ("block_used", ctypes.c_int32), ("team_wgs", ctypes.c_int32), ("team_threads", ctypes.c_int32),
                 ("refreshes", ctypes.c_int32), ("sweep_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
-                ("kernel_kind", ctypes.c_int32)]
+                ("kernel_kind", ctypes.c_int32), ("diverged", ctypes.c_int32), ("rel_grad", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -90,14 +93,17 @@ _SIGS = {
                                                _dp, _IP, _vp]),
     "hpscd_autotune_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Sys), _vp, _vp, _OP, _vp, _vp]),
     "hpscd_abort": (ctypes.c_int, [_vp]),
+    "hpscd_select_f32": (ctypes.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _i32, ctypes.c_double, _vp,
+                                        ctypes.POINTER(ctypes.c_int32), _dp, _dp, ctypes.POINTER(ctypes.c_int32),
+                                        _vp]),
     "hpscd_batched_plan_create": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Sys), _vp, _vp, _vp, _OP, _vp,
                                                  ctypes.POINTER(_vp)]),
     "hpscd_batched_plan_launch": (ctypes.c_int, [_vp, _vp]),
     "hpscd_batched_plan_results": (ctypes.c_int, [_vp, _dp, ctypes.POINTER(ctypes.c_int32),
                                                   ctypes.POINTER(ctypes.c_int32), _dp, _IP, _vp]),
     "hpscd_batched_plan_destroy": (None, [_vp]),
-    "hpscd_mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                        ctypes.POINTER(_vp)]),
+    "hpscd_mlp_create": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_uint64, ctypes.POINTER(_vp)]),
     "hpscd_mlp_destroy": (None, [_vp]),
     "hpscd_mlp_num_params": (_i64, [_vp]),
     "hpscd_mlp_set_params": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -106,6 +112,9 @@ _SIGS = {
     "hpscd_mlp_grads": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_float), _vp]),
     "hpscd_mlp_train_step": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_float,
                                             ctypes.POINTER(ctypes.c_float), _vp]),
+    "hpscd_mlp_fit_output_scaling": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
+    "hpscd_mlp_get_output_scaling": (ctypes.c_int, [_vp, _vp, _vp]),
+    "hpscd_mlp_set_output_scaling": (ctypes.c_int, [_vp, _vp, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -129,13 +138,15 @@ def last_error() -> str:
 
 
 def make_opts(max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols=0, refresh_cols=0, block=0, flags=0,
-              team_threads=0, depth=0) -> Opts:
+              team_threads=0, depth=0, thr=0, order_ptr=0) -> Opts:
     o = Opts()
     _lib.hpscd_default_opts(ctypes.byref(o))
     o.max_sweeps, o.stop, o.tol = int(max_sweeps), int(stop), float(tol)
     o.check_cols, o.refresh_cols, o.block, o.flags = int(check_cols), int(refresh_cols), int(block), int(flags)
     o.team_threads = int(team_threads)
     o.depth = int(depth)
+    o.thr = int(thr)
+    o.order = int(order_ptr) or None
     return o
 
 
@@ -146,6 +157,36 @@ def validate(m, n, X_ptr, ldx, elem_bytes, y_ptr, opts: Opts, a_ptr) -> int:
 
 # --------------------------------------------------------------- device side
 _CTX = {}
+_LIVE = weakref.WeakSet()   # plans and networks still holding library objects
+_SHUTDOWN = False
+
+
+def _shutdown():
+    """Release every library object while the HIP runtime (and a profiler
+    wrapped around the process) is still fully up: Python's atexit hooks run
+    before the interpreter tears modules down and before the C runtime's own
+    exit handlers, where the runtime and any tool attached to it finalise.
+    Objects collected later find the flag set and release nothing."""
+    global _SHUTDOWN
+    if _SHUTDOWN:
+        return
+    _SHUTDOWN = True
+    try:
+        torch = _torch()
+        if torch.cuda.is_available() and torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    except Exception:
+        pass
+    for obj in list(_LIVE):
+        try:
+            obj.close()
+        except Exception:
+            pass
+    for dev in list(_CTX):
+        _lib.hpscd_destroy(_CTX.pop(dev))
+
+
+atexit.register(_shutdown)
 
 
 def _torch():
@@ -191,18 +232,26 @@ class Result:
 
 
 def solve(Xt, y, a0=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols=0, block=0, flags=0,
-          team_threads=0, depth=0, want_hist=True) -> Result:
+          team_threads=0, depth=0, want_hist=True, thr=0, order=None) -> Result:
     """Solve X·a = y (Algorithm 1, single precision) on the GPU.
 
-    Xt: (n, ldx) float32 CUDA tensor (column j of X in Xt[j, :m]); y: (m,)."""
+    Xt: (n, ldx) float32 CUDA tensor (column j of X in Xt[j, :m]); y: (m,).
+    thr > 1: the parallel solver (Algorithm 2) with blocks of thr columns.
+    order: None (cyclic) or an int32 CUDA tensor (>= max_sweeps, n) whose
+    row s-1 lists the columns of sweep s."""
     torch = _torch()
     _need_cuda(Xt, "Xt", torch.float32)
     _need_cuda(y, "y", torch.float32)
     _need_cuda(a0, "a0", torch.float32)
     n, ldx = Xt.shape
     m = y.numel()
+    if order is not None:
+        _need_cuda(order, "order", torch.int32)
+        if order.dim() != 2 or order.shape[1] != n or order.shape[0] < max_sweeps:
+            raise ValueError("order must have shape (>= max_sweeps, n)")
     a = torch.empty(n, dtype=torch.float32, device=Xt.device)
-    opts = make_opts(max_sweeps, stop, tol, check_cols, 0, block, flags, team_threads, depth)
+    opts = make_opts(max_sweeps, stop, tol, check_cols, 0, block, flags, team_threads, depth, thr,
+                     order.data_ptr() if order is not None else 0)
     hist = np.full(max_sweeps + 1, np.nan) if want_hist else None
     info = Info()
     _check(_lib.hpscd_solve_f32(context(Xt.device.index), m, n, _ptr(Xt), ldx, _ptr(y), _ptr(a0),
@@ -211,6 +260,37 @@ def solve(Xt, y, a0=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols
                                 ctypes.byref(info), _stream()))
     h = hist[: info.sweeps_done + 1] if hist is not None else None
     return Result(a, h, info.as_dict())
+
+
+@dataclass
+class SelectResult:
+    a: object          # torch tensor (n,) float32: a0 plus the selected steps
+    J: list            # selected columns, in order
+    da: np.ndarray     # step taken for each selected column
+    hist: np.ndarray   # ||e|| before the first and after each selection
+    count: int
+
+
+def select(Xt, y, F, a0=None, *, tol=0.0) -> SelectResult:
+    """Feature selection with HPSCD (Algorithm 3) on the GPU: F greedy
+    choices of the column whose one-column step lowers ||e|| most."""
+    torch = _torch()
+    _need_cuda(Xt, "Xt", torch.float32)
+    _need_cuda(y, "y", torch.float32)
+    _need_cuda(a0, "a0", torch.float32)
+    n, ldx = Xt.shape
+    m = y.numel()
+    F = int(F)
+    a = torch.empty(n, dtype=torch.float32, device=Xt.device)
+    J = np.full(max(F, 1), -1, np.int32)
+    da = np.full(max(F, 1), np.nan)
+    hist = np.full(F + 1, np.nan)
+    cnt = ctypes.c_int32()
+    _check(_lib.hpscd_select_f32(context(Xt.device.index), m, n, _ptr(Xt), ldx, _ptr(y), _ptr(a0), F, float(tol),
+                                 _ptr(a), J.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), da.ctypes.data_as(_dp),
+                                 hist.ctypes.data_as(_dp), ctypes.byref(cnt), _stream()))
+    c = cnt.value
+    return SelectResult(a, [int(j) for j in J[:c]], da[:c].copy(), hist[: c + 1].copy(), c)
 
 
 def convert_bf16(Xt):
@@ -357,6 +437,7 @@ class BatchPlan:
                                               _ptr(ypool), _ptr(a0pool), ctypes.byref(opts), _ptr(self.a),
                                               ctypes.byref(h)))
         self._h = h
+        _LIVE.add(self)
 
     def launch(self):
         _check(_lib.hpscd_batched_plan_launch(self._h, _stream()))
@@ -379,6 +460,8 @@ class BatchPlan:
             self._h = None
 
     def __del__(self):
+        if _SHUTDOWN:
+            return
         try:
             self.close()
         except Exception:
@@ -406,14 +489,15 @@ class MLP:
     GELU on the hidden layers, linear output) with its Adam state.  All
     arithmetic runs in the library's kernels; tensors are FP32 on the device."""
 
-    def __init__(self, n_in, h1, h2, n_out, device: int | None = None):
+    def __init__(self, n_in, h1, h2, n_out, device: int | None = None, seed: int = 0):
         torch = _torch()
         self.device = torch.cuda.current_device() if device is None else int(device)
         self.shape = (int(n_in), int(h1), int(h2), int(n_out))
         h = _vp()
-        _check(_lib.hpscd_mlp_create(self.device, *self.shape, ctypes.byref(h)))
+        _check(_lib.hpscd_mlp_create(context(self.device), *self.shape, int(seed) & (2 ** 64 - 1), ctypes.byref(h)))
         self._h = h
         self.num_params = int(_lib.hpscd_mlp_num_params(h))
+        _LIVE.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -421,6 +505,8 @@ class MLP:
             self._h = None
 
     def __del__(self):
+        if _SHUTDOWN:
+            return
         try:
             self.close()
         except Exception:
@@ -439,6 +525,26 @@ class MLP:
         if flat.numel() != self.num_params:
             raise ValueError(f"expected {self.num_params} parameters")
         _check(_lib.hpscd_mlp_set_params(self._h, _ptr(flat), _stream()))
+
+    def fit_output_scaling(self, targets):
+        """Standardise the outputs by the per-output mean and sample standard
+        deviation of ``targets`` (count, n_out): see hpscd.h."""
+        targets = self._vec(targets, "targets", self.shape[3])
+        _check(_lib.hpscd_mlp_fit_output_scaling(self._h, targets.shape[0], _ptr(targets), _stream()))
+
+    def output_scaling(self):
+        """(2 * n_out,) device tensor [mu..., sd...]."""
+        torch = _torch()
+        t = torch.empty(2 * self.shape[3], dtype=torch.float32, device=f"cuda:{self.device}")
+        _check(_lib.hpscd_mlp_get_output_scaling(self._h, _ptr(t), _stream()))
+        return t
+
+    def set_output_scaling(self, mu_sd):
+        torch = _torch()
+        _need_cuda(mu_sd, "mu_sd", torch.float32)
+        if mu_sd.numel() != 2 * self.shape[3]:
+            raise ValueError(f"expected {2 * self.shape[3]} values")
+        _check(_lib.hpscd_mlp_set_output_scaling(self._h, _ptr(mu_sd), _stream()))
 
     def get_params(self):
         torch = _torch()

@@ -9,9 +9,10 @@ residual that a solve from zero reaches after K sweeps.
 Training labels are the solver's K-sweep iterates from zero (batched solve),
 the network is trained by the library's forward/backward/Adam kernels, and
 inference is one forward launch followed by a batched solve from a0.  This
-module only moves tensors between those calls; it never does the arithmetic
-of the solver or of the network itself.  The solve from zero remains the
-fallback: a0 only changes where the iteration starts, and the final FP64
+module only sequences those calls and indexes or moves tensors between them;
+it never does the arithmetic of the solver or of the network itself.  The
+solve from zero remains the fallback: every system that the initial guess
+did not bring to its tolerance is solved again from zero, and the final FP64
 check of every solve judges the result.
 """
 from __future__ import annotations
@@ -55,22 +56,9 @@ class WarmStart:
     def __init__(self, n_in: int, n_out: int, hidden=(256, 256), device: int | None = None, seed: int = 0):
         torch = _torch()
         self.shape = (int(n_in), int(hidden[0]), int(hidden[1]), int(n_out))
-        self.net = hpscd.MLP(*self.shape, device=device)
+        # parameters drawn by the library (uniform in +-1/sqrt(fan_in), seeded)
+        self.net = hpscd.MLP(*self.shape, device=device, seed=seed)
         self.device = torch.device("cuda", self.net.device)
-        self.set_params(torch.from_numpy(self.init_params(self.shape, seed)).to(self.device))
-
-    @staticmethod
-    def init_params(shape, seed: int) -> np.ndarray:
-        """Uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and biases, in the
-        library's flat layout."""
-        rng = np.random.default_rng(seed)
-        n_in, h1, h2, n_out = shape
-        parts = []
-        for fan_in, rows in ((n_in, h1), (h1, h2), (h2, n_out)):
-            b = 1.0 / math.sqrt(fan_in)
-            parts.append(rng.uniform(-b, b, rows * fan_in))
-            parts.append(rng.uniform(-b, b, rows))
-        return np.concatenate(parts).astype(np.float32)
 
     def set_params(self, flat):
         self.net.set_params(flat.contiguous())
@@ -82,22 +70,20 @@ class WarmStart:
             lr_final: float | None = None, seed: int = 0, log_every: int = 0):
         """Train on (feats, targets) with Adam on the mean squared error, the
         step size decaying from lr to lr_final (default lr/100) on a cosine
-        over the epochs.  The targets are standardised per output for training;
-        the scaling is folded into the last layer afterwards, so predict()
-        returns targets directly.  Returns the first-batch loss of each epoch
-        (standardised units)."""
+        over the epochs.  The library standardises the targets per output
+        (hpscd_mlp_fit_output_scaling) and returns predictions in target units.
+        Returns the first-batch loss of each epoch (standardised units)."""
         torch = _torch()
         N = feats.shape[0]
-        mu = targets.mean(0)
-        sd = targets.std(0).clamp_min(1e-12)
-        Ts = ((targets - mu) / sd).contiguous()
+        targets = targets.contiguous()
+        self.net.fit_output_scaling(targets)
         gen = torch.Generator().manual_seed(seed)
         hist = []
         lr_final = lr / 100.0 if lr_final is None else lr_final
         for ep in range(epochs):
             lr_ep = lr_final + (lr - lr_final) * 0.5 * (1.0 + math.cos(math.pi * ep / max(1, epochs)))
             perm = torch.randperm(N, generator=gen).to(self.device)
-            xs, ts = feats[perm].contiguous(), Ts[perm].contiguous()
+            xs, ts = feats[perm].contiguous(), targets[perm].contiguous()
             losses = []
             for b0 in range(0, N, batch):
                 b1 = min(N, b0 + batch)
@@ -108,17 +94,7 @@ class WarmStart:
             hist.append(float(np.mean(losses)))
             if log_every and (ep + 1) % log_every == 0:
                 print(f"epoch {ep + 1}: loss {hist[-1]:.4g}", flush=True)
-        self._fold_output_scaling(mu, sd)
         return hist
-
-    def _fold_output_scaling(self, mu, sd):
-        """o = sd * (W3 h + b3) + mu  ==  (sd W3) h + (sd b3 + mu)."""
-        n_in, h1, h2, n_out = self.shape
-        p = self.params()
-        w3 = p.numel() - n_out - n_out * h2
-        p[w3: w3 + n_out * h2] = (p[w3: w3 + n_out * h2].view(n_out, h2) * sd[:, None]).reshape(-1)
-        p[-n_out:] = p[-n_out:] * sd + mu
-        self.set_params(p)
 
     def predict(self, feats, out=None):
         """Initial guesses (count, n_out) for the systems with these features
@@ -126,7 +102,8 @@ class WarmStart:
         return self.net.forward(feats.contiguous(), out=out)
 
     def save(self, path: str):
-        np.savez(path, shape=np.asarray(self.shape, dtype=np.int64), params=self.params().cpu().numpy())
+        np.savez(path, shape=np.asarray(self.shape, dtype=np.int64), params=self.params().cpu().numpy(),
+                 scaling=self.net.output_scaling().cpu().numpy())
 
     @classmethod
     def load(cls, path: str, device: int | None = None) -> "WarmStart":
@@ -134,14 +111,45 @@ class WarmStart:
         with np.load(path, allow_pickle=False) as z:
             shape = tuple(int(v) for v in z["shape"])
             params = z["params"].astype(np.float32)
+            scaling = z["scaling"].astype(np.float32)
         ws = cls(shape[0], shape[3], hidden=shape[1:3], device=device)
         ws.set_params(torch.from_numpy(params).to(ws.device))
+        ws.net.set_output_scaling(torch.from_numpy(scaling).to(ws.device))
         return ws
 
 
-def solve_from(Xpool, ypool, table, a0=None, *, tols, max_sweeps: int):
+@dataclass
+class WarmResult:
+    a: object                 # (count * n,) FP32 device tensor: every system's result
+    sweeps: np.ndarray        # sweeps of the warm solve (plus those of the fallback where it ran)
+    converged: np.ndarray     # each system reached its tolerance
+    fallback: np.ndarray      # indices of the systems re-solved from zero
+    final_rel_resid: np.ndarray
+
+
+def solve_from(Xpool, ypool, table, a0=None, *, tols, max_sweeps: int, fallback: bool = True) -> WarmResult:
     """Batched solve of every system until ||e|| < tols[i]·||y|| (at most
-    max_sweeps sweeps), from a0 (count, n) or from zero."""
+    max_sweeps sweeps), from a0 (count, n) or from zero.  With ``fallback``,
+    every system that a0 did not bring to its tolerance is solved again from
+    zero (one more batched launch over those systems): the solve from zero is
+    the result of record wherever the initial guess did not pay off."""
+    torch = _torch()
+    table = np.asarray(table, dtype=np.int64).reshape(-1, 6)
+    tols = np.asarray(tols, dtype=np.float64).reshape(-1)
     a0pool = None if a0 is None else a0.reshape(-1).contiguous()
-    return hpscd.solve_batched(Xpool, ypool, table, a0pool, max_sweeps=max_sweeps, stop=hpscd.STOP_REL_RESID,
-                               tols=tols)
+    r = hpscd.solve_batched(Xpool, ypool, table, a0pool, max_sweeps=max_sweeps, stop=hpscd.STOP_REL_RESID,
+                            tols=tols)
+    a = r.a
+    sweeps, conv, fr = r.sweeps.copy(), r.converged.copy(), r.final_rel_resid.copy()
+    missed = np.flatnonzero(conv == 0) if (fallback and a0 is not None) else np.zeros(0, np.int64)
+    if missed.size:
+        sub = table[missed]
+        r0 = hpscd.solve_batched(Xpool, ypool, sub, None, max_sweeps=max_sweeps, stop=hpscd.STOP_REL_RESID,
+                                 tols=tols[missed], a_size=a.numel())
+        idx = torch.from_numpy(np.concatenate([np.arange(o, o + k) for o, k in zip(sub[:, 5], sub[:, 1])]))
+        idx = idx.to(a.device)
+        a[idx] = r0.a[idx]
+        sweeps[missed] += r0.sweeps
+        conv[missed] = r0.converged
+        fr[missed] = r0.final_rel_resid
+    return WarmResult(a, sweeps, conv, missed, fr)

@@ -41,9 +41,11 @@ def test_struct_layouts_match_header(hp):
 #include <stddef.h>
 #include "hpscd.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hpscd_opts), sizeof(hpscd_info), sizeof(hpscd_sys),
-         offsetof(hpscd_opts, tol), offsetof(hpscd_info, final_norm), offsetof(hpscd_info, total_ms),
-         offsetof(hpscd_sys, tol), offsetof(hpscd_info, kernel_kind));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hpscd_opts), sizeof(hpscd_info),
+         sizeof(hpscd_sys), offsetof(hpscd_opts, tol), offsetof(hpscd_info, final_norm),
+         offsetof(hpscd_info, total_ms), offsetof(hpscd_sys, tol), offsetof(hpscd_info, kernel_kind),
+         offsetof(hpscd_opts, thr), offsetof(hpscd_opts, order), offsetof(hpscd_info, diverged),
+         offsetof(hpscd_info, rel_grad));
   return 0;
 }
 '''
@@ -55,11 +57,12 @@ int main(void) {
         got = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     assert got == [ctypes.sizeof(hp.Opts), ctypes.sizeof(hp.Info), ctypes.sizeof(hp.Sys),
                    hp.Opts.tol.offset, hp.Info.final_norm.offset, hp.Info.total_ms.offset, hp.Sys.tol.offset,
-                   hp.Info.kernel_kind.offset]
+                   hp.Info.kernel_kind.offset, hp.Opts.thr.offset, hp.Opts.order.offset, hp.Info.diverged.offset,
+                   hp.Info.rel_grad.offset]
 
 
 def test_version(hp):
-    assert hp._lib.hpscd_version() == 1
+    assert hp._lib.hpscd_version() == 2
 
 
 @pytest.mark.parametrize("case,msg", [
@@ -79,11 +82,19 @@ def test_version(hp):
     (dict(block=3), "block"),
     (dict(block=32), "block"),
     (dict(flags=2 | 4), "exclusive"),
+    (dict(thr=-1), "thr"),
+    (dict(thr=4, order=256), "exclusive"),
+    (dict(thr=4, depth=5), "wide-block kernel"),
+    (dict(order=256, depth=2), "wide-block kernel"),
+    (dict(thr=4, block=8), "blocks of 16"),
+    (dict(order=256, refresh=64), "refreshes"),
 ])
 def test_validation_rejects(hp, case, msg):
-    kw = dict(m=100, n=10, X=4096, ldx=100, elem=4, y=64, a=128, max_sweeps=5, stop=0, tol=0.0, block=0, flags=0)
+    kw = dict(m=100, n=10, X=4096, ldx=100, elem=4, y=64, a=128, max_sweeps=5, stop=0, tol=0.0, block=0, flags=0,
+              thr=0, order=0, depth=0, refresh=0)
     kw.update(case)
-    o = hp.make_opts(kw["max_sweeps"], kw["stop"], kw["tol"], 0, 0, kw["block"], kw["flags"])
+    o = hp.make_opts(kw["max_sweeps"], kw["stop"], kw["tol"], 0, kw["refresh"], kw["block"], kw["flags"],
+                     depth=kw["depth"], thr=kw["thr"], order_ptr=kw["order"])
     st = hp.validate(kw["m"], kw["n"], kw["X"], kw["ldx"], kw["elem"], kw["y"], o, kw["a"])
     assert st == hp.EINVAL
     assert msg in hp.last_error()
@@ -93,15 +104,18 @@ def test_validation_accepts(hp):
     o = hp.make_opts(5)
     assert hp.validate(100, 10, 4096, 100, 4, 64, o, 128) == hp.OK
     assert hp.validate(100, 10, 4096, 104, 2, 64, o, 128) == hp.OK
+    for kw in (dict(stop=hp.STOP_REL_GRAD, tol=1e-6), dict(thr=50), dict(thr=1, depth=5), dict(order_ptr=256),
+               dict(thr=7, depth=8, block=16)):
+        assert hp.validate(100, 10, 4096, 100, 4, 64, hp.make_opts(5, **kw), 128) == hp.OK, kw
 
 
-@pytest.mark.parametrize("depth", [0, 2, 3, 4, 5, 6, 7, 8, 12, 13])
+@pytest.mark.parametrize("depth", [0, 2, 3, 4, 5, 8])
 def test_kernel_kinds_accepted(hp, depth):
     o = hp.make_opts(5, depth=depth)
     assert hp.validate(100, 10, 4096, 100, 4, 64, o, 128) == hp.OK
 
 
-@pytest.mark.parametrize("depth", [1, 9, 11, 14, -1])
+@pytest.mark.parametrize("depth", [1, 6, 7, 9, 11, 12, 13, 14, -1])
 def test_unknown_kernel_kind_rejected(hp, depth):
     o = hp.make_opts(5, depth=depth)
     assert hp.validate(100, 10, 4096, 100, 4, 64, o, 128) == hp.EINVAL
@@ -151,9 +165,12 @@ def test_single_hip_runtime_shared_with_torch(hp):
 
 def test_mlp_create_rejects_bad_widths(hp):
     h = ctypes.c_void_p()
-    assert hp._lib.hpscd_mlp_create(0, 13, 0, 256, 64, ctypes.byref(h)) == hp.EINVAL
+    assert hp._lib.hpscd_mlp_create(16, 13, 0, 256, 64, 0, ctypes.byref(h)) == hp.EINVAL
     assert "widths" in hp.last_error()
-    assert hp._lib.hpscd_mlp_create(0, 13, 256, 256, 64, None) == hp.EINVAL
+    assert hp._lib.hpscd_mlp_create(None, 13, 256, 256, 64, 0, ctypes.byref(h)) == hp.EINVAL
+    assert "ctx" in hp.last_error()
+    assert hp._lib.hpscd_mlp_create(16, 13, 256, 256, 64, 0, None) == hp.EINVAL
+    assert hp._lib.hpscd_mlp_fit_output_scaling(None, 1, 16, None) == hp.EINVAL
     assert hp._lib.hpscd_mlp_num_params(None) == 0
     assert hp._lib.hpscd_mlp_forward(None, 1, 16, 16, None) == hp.EINVAL
     hp._lib.hpscd_mlp_destroy(None)
@@ -178,3 +195,21 @@ def test_wide_block_needs_the_wide_kernel(hp):
     assert hp.validate(100, 10, 4096, 100, 4, 64, hp.make_opts(5, block=16), 128) == hp.OK
     assert hp.validate(100, 10, 4096, 100, 4, 64, hp.make_opts(5, block=16, depth=5), 128) == hp.EINVAL
     assert "depth 8" in hp.last_error()
+
+
+def test_select_rejects_bad_arguments(hp):
+    J = (ctypes.c_int32 * 4)()
+    cnt = ctypes.c_int32()
+    args = dict(ctx=16, m=100, n=10, X=4096, ldx=100, y=64, a0=None, F=3, tol=0.0, a=128, J=J, cnt=ctypes.byref(cnt))
+
+    def call(**kw):
+        a = dict(args)
+        a.update(kw)
+        return hp._lib.hpscd_select_f32(a["ctx"], a["m"], a["n"], a["X"], a["ldx"], a["y"], a["a0"], a["F"],
+                                        a["tol"], a["a"], a["J"], None, None, a["cnt"], None)
+
+    for kw, msg in ((dict(ctx=None), "ctx"), (dict(m=0), "m and n"), (dict(X=None), "must not be NULL"),
+                    (dict(J=None), "J_out"), (dict(ldx=98), "ldx"), (dict(X=4100), "ldx"), (dict(F=-1), "F must"),
+                    (dict(tol=float("inf")), "tol"), (dict(tol=-0.5), "tol")):
+        assert call(**kw) == hp.EINVAL, kw
+        assert msg in hp.last_error(), (kw, hp.last_error())

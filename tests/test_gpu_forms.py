@@ -125,14 +125,15 @@ def test_batched_stop_and_warm_start(lib):
         assert r2.hist[i][1] <= r2.hist[i][0] * (1 + 1e-6)
 
 
-def test_bf16_pipelined_refresh_mid_sweep(lib):
-    """Refresh every 16 column steps on a 32-column system: each launch ends
-    inside a sweep and retires its last pipelined block before the refresh."""
+def test_bf16_ring_refresh_mid_sweep(lib):
+    """Refresh every 16 column steps on a 32-column system: each launch of the
+    grid kernel ends inside a sweep, and the next one starts from the
+    refreshed residual."""
     s = gen.tall_large(m=100_000, n=32, seed=9)
     X32 = dev(s.Xt)
     Xb = lib.convert_bf16(X32)
-    say("bf16 pipelined")
-    r = lib.solve_bf16(Xb, X32, dev(s.y), max_sweeps=4, refresh_cols=16, block=4, depth=4)
+    say("bf16 ring mid sweep")
+    r = lib.solve_bf16(Xb, X32, dev(s.y), max_sweeps=4, refresh_cols=16, block=4, depth=2)
     ref = oracle.solve_bf16_refresh(s.Xt, s.y, s.m, max_sweeps=4, refresh_cols=16)
     assert r.info["refreshes"] == ref.refreshes == 8
     assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5, r.info
@@ -159,12 +160,14 @@ def test_bf16_time_to_tolerance_is_confirmed(lib, size):
                        refresh_cols=refresh, block=8)
     ref = oracle.solve_bf16_refresh(s.Xt, s.y, s.m, max_sweeps=3, stop=oracle.STOP_REL_RESID, tol=tol,
                                     check_cols=check, refresh_cols=refresh)
+    say("cols", r.info["cols_done"], ref.cols, "refreshes", r.info["refreshes"], ref.refreshes)
     assert ref.converged and r.info["converged"] == 1
     assert r.info["final_rel_resid"] < tol
-    assert abs(r.info["cols_done"] - ref.cols) <= check
-    assert abs(r.info["refreshes"] - ref.refreshes) <= 1
-    if r.info["cols_done"] == ref.cols:
-        assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
+    # the stop lands on the same column check, after the same refreshes, and
+    # the iterates agree there
+    assert r.info["cols_done"] == ref.cols
+    assert r.info["refreshes"] == ref.refreshes
+    assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
 
 
 def test_batched_graph_replays_match_eager(lib):
@@ -264,11 +267,11 @@ def test_bf16_polling_wave_kernel(lib):
     assert np.all(np.abs(np.asarray(r.hist) - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0])
 
 
-@pytest.mark.parametrize("kind", [6, 7, 8])
-def test_bf16_blocks_in_flight_kernel(lib, kind):
-    """The storage form through the grid kernel with a ring of two (kind 6)
-    or three (kind 7) column blocks, with refreshes between launch segments,
-    against the oracle of the form."""
+@pytest.mark.parametrize("kind", [3, 8])
+def test_bf16_grid_kernel_kinds(lib, kind):
+    """The storage form through the grid kernel with a ring of three column
+    blocks (kind 3) and through the wide-block kernel (kind 8), with
+    refreshes between launch segments, against the oracle of the form."""
     s = gen.tall_large(m=150_000, n=48 if kind == 8 else 40, seed=23)
     X32 = dev(s.Xt)
     Xb = lib.convert_bf16(X32)

@@ -1,9 +1,20 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
 same seeded inputs, after the same number of sweeps.
 
-Tolerance for single precision: ||a_gpu - a_oracle|| / ||a_oracle|| <= 1e-5
-and every hist entry within 1e-5·hist[0], the oracle running on the FP32
-input values.
+Bounds for single precision (the oracle runs on the FP32 input values):
+* a: ||a_gpu - a_ora|| / ||a_ora|| <= 1e-5, and every coordinate
+  |a_gpu,j - a_ora,j| <= 1e-5 ||a_ora||_inf;
+* hist, sweep by sweep: |h_gpu[s] - h_ora[s]| <= 1e-5 h_ora[s] + 4 u h_ora[0]
+  with u = 2^-24: the running residual is stored in FP32, so every entry
+  carries a rounding error of the order of u times the entries it was
+  formed from (|y_i| at the start); once ||e|| has fallen far below ||y||
+  its norm is only resolved to about u ||y|| (the FP64 final check, below,
+  is the exact value);
+* final FP64 check: the reported ||y - X a|| / ||y|| equals the FP64 oracle's
+  value for the returned coefficients to 1e-8 relative (1e-13 absolute: FP64
+  sums in another order of terms up to ||y||), and differs from the
+  oracle's own iterate's by at most ||X (a_gpu - a_ora)|| / ||y|| (triangle
+  inequality).
 """
 import math
 
@@ -16,6 +27,7 @@ from workloads import gen
 pytestmark = pytest.mark.gpu
 
 TOL_A = 1e-5
+U32 = 2.0 ** -24
 
 
 def dev(x):
@@ -39,16 +51,51 @@ def run(lib, s, sweeps, **kw):
     return r
 
 
-def check(lib, s, sweeps, tol=TOL_A, **kw):
+def check_a(a, ref_a, tol=TOL_A, info=None):
+    """Norm-wise and coordinate-wise agreement of the coefficients."""
+    a = np.asarray(a, np.float64)
+    ref_a = np.asarray(ref_a, np.float64)
+    e = rel(a, ref_a)
+    assert e <= tol, (e, info)
+    scale = float(np.max(np.abs(ref_a))) if ref_a.size else 1.0
+    worst = float(np.max(np.abs(a - ref_a))) / (scale if scale > 0 else 1.0) if a.size else 0.0
+    assert worst <= tol, (worst, int(np.argmax(np.abs(a - ref_a))), info)
+
+
+def check_hist(h, ref_hist):
+    """Sweep-by-sweep agreement of ||e||, each entry against its own value."""
+    h = np.asarray(h, np.float64)
+    ref = np.asarray(ref_hist, np.float64)
+    assert len(h) == len(ref), (len(h), len(ref))
+    bound = 1e-5 * ref + 4 * U32 * ref[0]
+    bad = np.flatnonzero(np.abs(h - ref) > bound)
+    assert bad.size == 0, (bad[:5], h[bad[:5]], ref[bad[:5]])
+
+
+def check_final(r, s, ref_a):
+    """The FP64 final check: exact for the returned coefficients, and within
+    the triangle-inequality bound of the oracle iterate's residual."""
+    a = r.a.cpu().numpy().astype(np.float64)
+    fr = r.info["final_rel_resid"]
+    direct = oracle.final_rel_resid(s.Xt, s.y, s.m, a)
+    # (FP64 sums in another order: 1e-8 relative, plus the rounding of terms
+    # as large as ||y|| when the residual is far smaller)
+    assert fr == pytest.approx(direct, rel=1e-8, abs=1e-13), (fr, direct)
+    ynorm = np.linalg.norm(np.asarray(s.y[: s.m], np.float64))
+    dx = np.linalg.norm(oracle.residual(s.Xt, np.zeros(s.m), s.m, a - ref_a))
+    fr_ora = oracle.final_rel_resid(s.Xt, s.y, s.m, ref_a)
+    assert abs(fr - fr_ora) <= dx / ynorm * (1 + 1e-6) + 1e-12 * fr_ora, (fr, fr_ora, dx / ynorm)
+
+
+def check(lib, s, sweeps, tol=TOL_A, final=True, **kw):
     a0 = kw.get("a0")
     r = run(lib, s, sweeps, **kw)
     ref = oracle.solve(s.Xt, s.y, s.m, a0=a0, max_sweeps=sweeps)
-    a = r.a.cpu().numpy()
-    e = rel(a, ref.a)
-    assert e <= tol, (e, r.info)
-    h = np.asarray(r.hist)
-    assert len(h) == sweeps + 1
-    assert np.all(np.abs(h - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0]), (h[:4], ref.hist[:4])
+    check_a(r.a.cpu().numpy(), ref.a, tol, r.info)
+    assert len(r.hist) == sweeps + 1
+    check_hist(r.hist, ref.hist)
+    if final:
+        check_final(r, s, ref.a)
     return r, ref
 
 
@@ -99,7 +146,7 @@ def test_ragged_shapes(lib, m, n):
 
 
 @pytest.mark.parametrize("m", [3, 4097, 8195])
-@pytest.mark.parametrize("kind", [5, 6, 7, 8])
+@pytest.mark.parametrize("kind", [2, 3, 5, 8])
 def test_grid_kinds_tiny_last_workgroup(lib, m, kind):
     """Grids whose last workgroup holds fewer valid rows than one chunk (or
     systems below one chunk), NaN padding rows: the chunks with no valid row
@@ -107,7 +154,7 @@ def test_grid_kinds_tiny_last_workgroup(lib, m, kind):
     say("tiny last workgroup", m, kind)
     rng = np.random.default_rng(m + kind)
     s = gen.make_system(rng, m, 21, noise=0.01, pad=np.nan)
-    check(lib, s, 6, flags=lib.F_FORCE_GRID, depth=kind, block=16 if kind == 8 else 8)
+    check(lib, s, 6, flags=lib.F_FORCE_GRID, depth=kind, block=16 if kind == 8 else (4 if kind < 5 else 8))
 
 
 def test_tall_grid_multi_wg(lib):
@@ -126,11 +173,10 @@ def test_tall_large_full_size_two_sweeps(lib):
     say("tall_large full size")
     r, ref = check(lib, s, 2)
     say("info", r.info)
-    for kind in (12, 13):
-        check(lib, s, 2, block=4, depth=kind)
-    for kind, tt in ((6, 512), (6, 1024), (7, 512), (8, 512)):
-        say("column blocks in flight", kind, tt)
-        r, _ = check(lib, s, 2, depth=kind, team_threads=tt)
+    assert r.info["kernel_kind"] == 8 and r.info["team_wgs"] == 256
+    for kind, tt, block in ((5, 256, 8), (5, 512, 4), (3, 512, 4)):
+        say("grid kind", kind, tt, block)
+        r, _ = check(lib, s, 2, depth=kind, team_threads=tt, block=block)
         assert r.info["kernel_kind"] == kind and r.info["team_threads"] == tt
 
 
@@ -254,13 +300,11 @@ def test_residual_f64(lib):
 
 # ------------------------------------------------------------ pipelined grid
 
-@pytest.mark.parametrize("block,kind", [(2, 4), (4, 4), (4, 12), (4, 13), (8, 12), (8, 5), (4, 5), (8, 6), (4, 6),
-                                        (8, 7), (4, 7), (16, 8)])
+@pytest.mark.parametrize("block,kind", [(1, 2), (2, 2), (4, 2), (4, 3), (8, 3), (8, 5), (4, 5), (16, 8)])
 def test_grid_kernel_kinds_match_oracle(lib, block, kind):
-    """Every grid kernel kind (pipelined reductions with the cross-block Gram
-    correction; warp-specialised with a two- or three-block ring; polling
-    waves fed through LDS; two blocks in flight) produces the iterates of
-    Algorithm 1 (n not a multiple of the block, ragged rows)."""
+    """Every grid kernel kind (prefetch rings of two or three blocks; polling
+    waves fed through LDS; 16-column blocks through the step matrix) produces
+    the iterates of Algorithm 1 (n not a multiple of the block, ragged rows)."""
     s = gen.tall_large(m=300_003, n=37, seed=13, pad=np.nan)
     say("grid kind", block, kind)
     r, ref = check(lib, s, 6, block=block, depth=kind)
@@ -306,20 +350,27 @@ def test_wide_kernel_one_workgroup_resid_stop(lib):
     assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
 
 
-def test_pipelined_grid_stop_rule(lib):
+def test_ring_grid_stop_rule(lib):
     s = gen.tall_large(m=250_000, n=48, seed=21)
-    say("pipelined stop")
-    r = run(lib, s, 100, block=4, depth=4, stop=lib.STOP_REL_CHANGE, tol=1e-6)
+    say("ring grid stop")
+    r = run(lib, s, 100, block=4, depth=3, stop=lib.STOP_REL_CHANGE, tol=1e-6)
     ref = oracle.solve(s.Xt, s.y, s.m, max_sweeps=100, tol=1e-6, stop=oracle.STOP_REL_CHANGE)
     assert r.info["converged"] == 1 and abs(r.info["sweeps_done"] - ref.sweeps) <= 1
-    check(lib, s, r.info["sweeps_done"], block=4, depth=4)
+    check(lib, s, r.info["sweeps_done"], block=4, depth=3)
 
 
-def test_pipelined_grid_warm_start(lib):
+def test_ring_grid_warm_start(lib):
     s = gen.tall_large(m=200_000, n=24, seed=5)
     a0 = np.random.default_rng(2).standard_normal(s.n).astype(np.float32)
-    say("pipelined warm")
-    check(lib, s, 3, a0=a0, block=4, depth=4)
+    say("ring grid warm")
+    check(lib, s, 3, a0=a0, block=4, depth=3)
+
+
+def test_depth4_is_one_workgroup_only(lib):
+    s = gen.tall_small(m=300, n=10)
+    with pytest.raises(lib.HPSCDError) as ei:
+        run(lib, s, 2, block=4, depth=4, flags=lib.F_FORCE_GRID)
+    assert ei.value.status == lib.EINVAL
 
 
 @pytest.mark.parametrize("team_threads", [256, 512])
@@ -341,15 +392,12 @@ def test_polling_wave_kernel_shapes(lib, team_threads):
     assert r.info["team_threads"] == team_threads and r.info["team_wgs"] > 1
 
 
-@pytest.mark.parametrize("kind,team_threads,m,n,stop", [(6, 512, 200_001, 45, "change"), (6, 1024, 120_013, 45, "change"),
-                                                         (6, 512, 100_003, 48, "resid"), (7, 512, 200_001, 45, "change"),
-                                                         (7, 512, 100_003, 48, "resid"), (7, 512, 99_999, 47, "change"),
+@pytest.mark.parametrize("kind,team_threads,m,n,stop", [(5, 512, 200_001, 45, "change"), (5, 512, 100_003, 48, "resid"),
                                                          (8, 512, 200_001, 45, "change"), (8, 512, 100_003, 48, "resid")])
 def test_blocks_in_flight_kernel(lib, kind, team_threads, m, n, stop):
-    """The grid kernel with one polling wave and a ring of two (kind 6) or
-    three (kind 7) column blocks, and the wide-block kernel (kind 8, 16
-    columns per reduction), on ragged systems with a warm start, stopping
-    inside the loop:
+    """The polling-wave grid kernel (kind 5, 8-column blocks) and the
+    wide-block kernel (kind 8, 16 columns per reduction), on ragged systems
+    with a warm start, stopping inside the loop:
     on the relative change of ||e|| at a sweep end, or on the relative
     residual at a column check inside a sweep.  The stop lands where the
     oracle's does and the iterate matches the oracle's after as many steps."""

@@ -202,3 +202,73 @@ def test_pins_catch_planted_mistakes(mutant, monkeypatch):
     else:
         monkeypatch.setattr(mo, "loss", lambda o, t: float(np.sum((np.asarray(o) - np.asarray(t)) ** 2)))
         assert fd_gradient_error() > 1e-3
+
+
+# ------------------------------------------------ initial parameters, output scaling
+
+def test_splitmix64_published_values():
+    """The SplitMix64 stream started at 0 begins 0xE220A8397B1DCDAF,
+    0x6E789E6AA1B965F4, 0x06C45D188009454F (the generator's widely published
+    reference outputs)."""
+    v = [int(x) for x in mo.splitmix64(0, [0, 1, 2])]
+    assert v == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_init_params_bounds_and_moments():
+    shape = (13, 256, 256, 64)
+    p = mo.init_params(shape, 5)
+    assert p.shape == (mo.num_params(shape),)
+    W1, b1, W2, b2, W3, b3 = mo.unpack(p, shape)
+    for w, fan in ((W1, 13), (b1, 13), (W2, 256), (b2, 256), (W3, 256), (b3, 256)):
+        bound = 1.0 / math.sqrt(fan)
+        assert np.all(np.abs(w) <= bound)
+    # uniform on [-b, b): mean 0, variance b^2 / 3
+    w = W2.ravel() * 16.0
+    assert abs(w.mean()) < 0.01 and abs(w.var() - 1.0 / 3.0) < 0.01
+    assert not np.array_equal(p, mo.init_params(shape, 6))
+
+
+def test_output_scaling_matches_torch():
+    rng = np.random.default_rng(3)
+    T = rng.standard_normal((500, 7)) * rng.uniform(0.1, 5, 7) + rng.uniform(-3, 3, 7)
+    mu, sd = mo.output_scaling(T)
+    tt = torch.from_numpy(T)
+    np.testing.assert_allclose(mu, tt.mean(0).numpy(), rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(sd, tt.std(0).numpy(), rtol=1e-12)
+
+
+def test_scaled_forward_equals_folded_network():
+    """sd * (W3 h + b3) + mu is the network whose last layer is
+    (diag(sd) W3, sd b3 + mu)."""
+    shape = (5, 12, 9, 4)
+    rng = np.random.default_rng(8)
+    p = rng.standard_normal(mo.num_params(shape)) * 0.3
+    mu, sd = rng.standard_normal(4), rng.uniform(0.5, 3, 4)
+    q = p.copy()
+    n_out, h2 = 4, 9
+    w3 = len(q) - n_out - n_out * h2
+    q[w3: w3 + n_out * h2] = (q[w3: w3 + n_out * h2].reshape(n_out, h2) * sd[:, None]).ravel()
+    q[-n_out:] = q[-n_out:] * sd + mu
+    x = rng.standard_normal((6, 5))
+    np.testing.assert_allclose(mo.forward_scaled(p, shape, x, mu, sd), mo.forward(q, shape, x), rtol=1e-12, atol=1e-12)
+
+
+def test_scaled_gradient_finite_differences():
+    shape = (4, 6, 5, 3)
+    rng = np.random.default_rng(9)
+    p = rng.standard_normal(mo.num_params(shape)) * 0.4
+    x = rng.standard_normal((7, 4))
+    t = rng.standard_normal((7, 3)) * 2 + 1
+    mu, sd = mo.output_scaling(t)
+    g, L = mo.grads_scaled(p, shape, x, t, mu, sd)
+
+    def lossf(q):
+        return mo.loss(mo.forward(q, shape, x), (t - mu) / sd)
+
+    assert L == pytest.approx(lossf(p), rel=1e-14)
+    h = 1e-6
+    for k in rng.choice(len(p), 12, replace=False):
+        e = np.zeros_like(p)
+        e[k] = h
+        fd = (lossf(p + e) - lossf(p - e)) / (2 * h)
+        assert g[k] == pytest.approx(fd, rel=1e-6, abs=1e-9)
