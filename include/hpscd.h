@@ -140,6 +140,25 @@ hpscd_status hpscd_solve_f32(hpscd_ctx* ctx, int64_t m, int64_t n, const float* 
                              const float* a0, const hpscd_opts* opts, float* a_out, double* hist,
                              hpscd_info* info, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): hpscd_solve_f32 with the
+ * same arguments, results and kernels, allocating nothing.  Its whole device
+ * workspace (control words, residual copies, column statistics, exchange
+ * words, partial sums, history) lies in a fixed scratch area of
+ * HPSCD_NOALLOC_SCRATCH_BYTES per device, which the library holds from the
+ * loading of its code on that device until the process ends; host results
+ * return through copies into the caller's memory (hist may be NULL; then
+ * info->diverged stays 0).  A solve whose workspace does not fit (about
+ * 8·m + 9 MB for a single-precision system; 4·m less without a0) returns
+ * HPSCD_EINVAL before any device work, naming the size.  Every call on one
+ * device shares that device's area, and it keeps the last call's contents:
+ * calls that overlap on one GPU (two streams, two threads, two contexts)
+ * race and must be serialised by the caller. */
+#define HPSCD_NOALLOC_SCRATCH_BYTES (64u << 20)
+hpscd_status hpscd_solve_f32_noalloc(hpscd_ctx* ctx, int64_t m, int64_t n, const float* X, int64_t ldx,
+                                     const float* y, const float* a0, const hpscd_opts* opts, float* a_out,
+                                     double* hist, hpscd_info* info, void* stream);
+
 /* Reduced-precision storage form: the sweeps read X rounded to bfloat16
  * (Xb, ldxb % 8 == 0) with FP32 products and residual; the starting residual,
  * every residual refresh (opts->refresh_cols) and the final check use the FP32

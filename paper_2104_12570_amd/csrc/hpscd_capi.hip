@@ -92,9 +92,18 @@ struct BatchWork {
 
 }  // namespace
 
+// Fixed workspace of hpscd_solve_f32_noalloc: one array per device, loaded
+// with the library's code object and kept until the process ends.  In host
+// code the name is a stand-in, not a device address: the address is taken
+// per device with hipGetSymbolAddress (hpscd_create) and only that pointer
+// is used.
+constexpr size_t kScratchBytes = (size_t)HPSCD_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 struct hpscd_ctx {
   int device = 0;
   int cus = 0;
+  unsigned char* scratch_ptr = nullptr;  // this device's copy of `scratch`
   DevBuf ctlb, e0, eo, a64, rdn, gram, cross, partial, slots, hist;
   DevBuf selw;  // feature selection: FP64 residual, inner products, flags, results
   BatchWork bw;
@@ -518,10 +527,10 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   CtlBlock* hc = ho.cb;
   double* hh = ho.hist;
   HIP_TRY(hipMemcpyAsync(hc, cb, sizeof(CtlBlock), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(hh, w.hist, (size_t)hist_len * 8, hipMemcpyDeviceToHost, st));
+  if (hh) HIP_TRY(hipMemcpyAsync(hh, w.hist, (size_t)hist_len * 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
 
-  if (hist && hist != hh) std::memcpy(hist, hh, (size_t)hist_len * 8);
+  if (hist && hh && hist != hh) std::memcpy(hist, hh, (size_t)hist_len * 8);
   if (info) {
     std::memset(info, 0, sizeof *info);
     info->sweeps_done = hc->ctl[CTL_SWEEPS];
@@ -540,8 +549,9 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
     info->total_ms = elapsed(c->ev[0], c->ev[3]);
     info->kernel_kind = pl.D;
     // ||e|| grew over a sweep (by more than 0.1 %)
-    for (int32_t k = 1; k <= info->sweeps_done && k < hist_len; ++k)
-      if (hh[k] > hh[k - 1] * 1.001) info->diverged = 1;
+    if (hh)
+      for (int32_t k = 1; k <= info->sweeps_done && k < hist_len; ++k)
+        if (hh[k] > hh[k - 1] * 1.001) info->diverged = 1;
     info->rel_grad = (grad_rule && info->sweeps_done > 0) ? hc->fstat[2] : std::numeric_limits<double>::quiet_NaN();
   }
   if (hc->ctl[CTL_NONFINITE]) return fail(HPSCD_ENONFINITE, "X or y holds a non-finite value");
@@ -549,6 +559,40 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   if (hc->ctl[CTL_ERR] == ERR_ABORTED) return fail(HPSCD_EABORTED, "solve aborted");
   if (hc->ctl[CTL_ERR] == ERR_NONFINITE) return fail(HPSCD_ENONFINITE, "the iteration produced a non-finite residual");
   g_err.clear();
+  return HPSCD_OK;
+}
+
+// Regions of the fixed scratch area for a solve planned as `pl`: the
+// context-path layout, with the partial sums limited to what the column
+// statistics of one 8192-way row split, the residual passes and the
+// gradient rule use, and no starting-residual buffer when a0 is absent.
+hpscd_status work_from_scratch(hpscd_ctx* c, const Plan& pl, int64_t m, int64_t n, const hpscd_opts* o, bool has_a0,
+                               Work* w) {
+  WorkSizes z = work_sizes(pl, m, n, o);
+  const int B = pl.B;
+  const int64_t nb = (n + B - 1) / B, NPX = B * (B + 1) / 2;
+  int64_t cap = std::max<int64_t>({(int64_t)8192 * NPX, nb * NPX, (m + 1023) / 1024 + 8});
+  if (o->stop == HPSCD_STOP_REL_GRAD) cap = std::max<int64_t>(cap, plan_xtv(m, n, (int64_t)1 << 22).need);
+  z.partial_cap = cap;
+  z.partial = (size_t)cap * 8;
+  if (!has_a0) z.e0 = 0;
+  if (B != 16) z.cross = 0;  // (step matrices: 16-column blocks only)
+  if (z.total() > kScratchBytes)
+    return fail(HPSCD_EINVAL, "the solve needs %zu bytes of workspace, more than the %zu-byte scratch area of the "
+                "allocation-free entry point", z.total(), kScratchBytes);
+  unsigned char* p = c->scratch_ptr;
+  auto take = [&](size_t b) { unsigned char* q = p; p += b; return q; };
+  w->cb = reinterpret_cast<CtlBlock*>(take(z.ctl));
+  w->e0 = reinterpret_cast<float*>(take(z.e0));
+  w->eo = reinterpret_cast<float*>(take(z.eo));
+  w->a64 = reinterpret_cast<double*>(take(z.a64));
+  w->rdn = reinterpret_cast<double*>(take(z.rdn));
+  w->gram = reinterpret_cast<double*>(take(z.gram));
+  w->cross = reinterpret_cast<double*>(take(z.cross));
+  w->partial = reinterpret_cast<double*>(take(z.partial));
+  w->slots = reinterpret_cast<uint64_t*>(take(z.slots));
+  w->hist = reinterpret_cast<double*>(take(z.hist));
+  w->partial_cap = cap;
   return HPSCD_OK;
 }
 
@@ -603,6 +647,15 @@ hpscd_status hpscd_create(int device, hpscd_ctx** out) {
     hpscd_ctx* c = new hpscd_ctx();
     c->device = device;
     c->cus = prop.multiProcessorCount;
+    {
+      void* sp = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !sp) {
+        delete c;
+        return fail(HPSCD_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      }
+      c->scratch_ptr = static_cast<unsigned char*>(sp);
+    }
     for (auto& e : c->ev)
       if (hipEventCreate(&e) != hipSuccess) { delete c; return fail(HPSCD_EDEVICE, "hipEventCreate"); }
     if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
@@ -645,6 +698,32 @@ hpscd_status hpscd_solve_f32(hpscd_ctx* ctx, int64_t m, int64_t n, const float* 
     if (rc != HPSCD_OK) return rc;
     if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
     return solve_single_ctx(ctx, m, n, X, ldx, false, X, ldx, y, a0, opts, a_out, hist, info, (hipStream_t)stream);
+  } catch (...) {
+    return fail(HPSCD_ENOMEM, "host allocation failure");
+  }
+}
+
+hpscd_status hpscd_solve_f32_noalloc(hpscd_ctx* ctx, int64_t m, int64_t n, const float* X, int64_t ldx,
+                                     const float* y, const float* a0, const hpscd_opts* opts, float* a_out,
+                                     double* hist, hpscd_info* info, void* stream) {
+  try {
+    hpscd_status rc = validate_single(m, n, X, ldx, 4, y, opts, a_out);
+    if (rc != HPSCD_OK) return rc;
+    if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
+    if (!ctx->scratch_ptr) return fail(HPSCD_EDEVICE, "the context has no scratch area");
+    hpscd_opts oo = *opts;
+    if (oo.max_sweeps == 0) oo.order = nullptr;
+    Plan pl;
+    if ((rc = plan_single(ctx, m, n, false, &oo, &pl)) != HPSCD_OK) return rc;
+    if (pl.V == 2 && n * (int64_t)(ldx * 4) > (int64_t)0xFFFFFFFF)
+      return fail(HPSCD_EINVAL, "a column order needs X below 4 GiB");
+    Work w;
+    if ((rc = work_from_scratch(ctx, pl, m, n, &oo, a0 != nullptr, &w)) != HPSCD_OK) return rc;
+    // results come back through pageable copies into the caller's memory
+    CtlBlock hcb;
+    HostOut ho{&hcb, hist};
+    return solve_single(ctx, m, n, X, ldx, false, X, ldx, y, a0, &oo, a_out, hist, info, (hipStream_t)stream, pl,
+                        w, ho);
   } catch (...) {
     return fail(HPSCD_ENOMEM, "host allocation failure");
   }

@@ -85,6 +85,7 @@ _SIGS = {
     "hpscd_destroy": (None, [_vp]),
     "hpscd_validate": (ctypes.c_int, [_i64, _i64, _vp, _i64, ctypes.c_int, _vp, _OP, _vp]),
     "hpscd_solve_f32": (ctypes.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _OP, _vp, _dp, _IP, _vp]),
+    "hpscd_solve_f32_noalloc": (ctypes.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _OP, _vp, _dp, _IP, _vp]),
     "hpscd_solve_bf16": (ctypes.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _OP, _vp, _dp, _IP, _vp]),
     "hpscd_convert_bf16": (ctypes.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _i64, _vp]),
     "hpscd_residual_f64": (ctypes.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _dp, _vp]),
