@@ -71,7 +71,9 @@ typedef struct {
   int32_t stop;         /* hpscd_stop */
   double tol;           /* finite, >= 0; ignored by HPSCD_STOP_NONE */
   int64_t check_cols;   /* >= 0, see HPSCD_STOP_REL_RESID (rounded to the block size) */
-  int64_t refresh_cols; /* bf16 form: e = y - X32·a (FP64 sums) every refresh_cols column steps; 0 = never */
+  int64_t refresh_cols; /* e = y - X32·a (FP64 sums) every refresh_cols column steps (X32 = X for
+                           hpscd_solve_f32); with HPSCD_STOP_REL_RESID a stop signalled by the running
+                           residual then holds only if the refreshed one passes too; 0 = never */
   int32_t block;        /* columns per reduction round (1, 2, 4, 8, or 16 with depth 8); 0 = library choice */
   int32_t flags;        /* HPSCD_F_* */
   int32_t team_threads; /* threads per workgroup; 0 = library choice.  Batched calls: 256
@@ -244,6 +246,13 @@ hpscd_status hpscd_batched_plan_launch(hpscd_batch_plan* plan, void* stream);
 hpscd_status hpscd_batched_plan_results(hpscd_batch_plan* plan, double* hist, int32_t* sweeps_done,
                                         int32_t* converged, double* final_rel_resid, hpscd_info* info, void* stream);
 void hpscd_batched_plan_destroy(hpscd_batch_plan* plan);
+
+/* Measured denominator of the bandwidth roofline: average device time of one
+ * pass of 16-byte loads over `bytes` of the device buffer `buf` (16-byte
+ * aligned, bytes a multiple of 16) over `passes` passes after one untimed
+ * pass; the loaded data is summed and discarded.  Returns after the passes. */
+hpscd_status hpscd_read_stream(hpscd_ctx* ctx, const void* buf, int64_t bytes, int32_t passes, double* ms_per_pass,
+                               void* stream);
 
 /* Ask a running solve on this context to stop at its next sweep boundary;
  * that solve returns HPSCD_EABORTED.  Safe to call from another thread. */

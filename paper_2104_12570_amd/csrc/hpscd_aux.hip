@@ -230,6 +230,7 @@ __global__ void __launch_bounds__(256) k_gram16(const double* gram8, const doubl
 // this block; the substitution removes exactly those:
 //     da_l = (g_l - sum_{i < s_l - j0} <X_l, X_i> da_i) / <X_l, X_l>.
 // thr = 1 is the substitution of Algorithm 1.
+template <bool PAR>
 __global__ void __launch_bounds__(256) k_block_inverse16(const double* rdn, const double* gram, int64_t nb,
                                                          double* minv, int32_t thr, const int32_t* done) {
   if (done && load_flag(done)) return;
@@ -240,16 +241,19 @@ __global__ void __launch_bounds__(256) k_block_inverse16(const double* rdn, cons
   double x[16];
 #pragma unroll
   for (int l = 0; l < 16; ++l) {
-    int upto = l;  // Algorithm 1: every earlier column of the block
-    if (thr > 1) {
+    double acc = (l == k) ? 1.0 : 0.0;
+    if constexpr (PAR) {
       const int64_t j0 = b * 16;
       const int64_t s_l = (j0 + l) / thr * thr;
-      upto = s_l < j0 ? 0 : (int)(s_l - j0);
-    }
-    double acc = (l == k) ? 1.0 : 0.0;
+      const int upto = s_l < j0 ? 0 : (int)(s_l - j0);
 #pragma unroll
-    for (int i = 0; i < l; ++i)
-      if (i < upto) acc -= gram[b * 120 + l * (l - 1) / 2 + i] * x[i];
+      for (int i = 0; i < l; ++i)
+        if (i < upto) acc -= gram[b * 120 + l * (l - 1) / 2 + i] * x[i];
+    } else {
+      // Algorithm 1: every earlier column of the block
+#pragma unroll
+      for (int i = 0; i < l; ++i) acc -= gram[b * 120 + l * (l - 1) / 2 + i] * x[i];
+    }
     x[l] = acc * rdn[b * 16 + l];
     minv[(b * 16 + l) * 16 + k] = x[l];
   }
@@ -258,8 +262,11 @@ __global__ void __launch_bounds__(256) k_block_inverse16(const double* rdn, cons
 static hipError_t block_inverse16(const double* rdn, const double* gram, int64_t n, double* minv, hipStream_t s,
                                   int32_t thr = 0, const int32_t* done = nullptr) {
   const int64_t nb = (n + 15) / 16;
-  hipLaunchKernelGGL(k_block_inverse16, dim3((unsigned)((nb * 16 + 255) / 256)), dim3(256), 0, s, rdn, gram, nb,
-                     minv, thr, done);
+  const dim3 grid((unsigned)((nb * 16 + 255) / 256));
+  if (thr > 1)
+    hipLaunchKernelGGL(k_block_inverse16<true>, grid, dim3(256), 0, s, rdn, gram, nb, minv, thr, done);
+  else
+    hipLaunchKernelGGL(k_block_inverse16<false>, grid, dim3(256), 0, s, rdn, gram, nb, minv, thr, done);
   return hipGetLastError();
 }
 
@@ -685,6 +692,36 @@ hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, int64_t rows, int
   const int64_t total = (rows + 7) / 8 * cols;
   hipLaunchKernelGGL(k_f32_to_bf16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, rows, cols,
                      lds, ldd);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ read stream
+// Reads every 16-byte chunk of a buffer once per pass (grid-stride, eight
+// 128-bit loads in flight per thread), the bandwidth a pure read stream of
+// HBM reaches: the measured denominator of the sweep kernels' roofline.
+// The loaded values only feed a sum that is stored when it is NaN (never
+// for the finite data it is used on), so no load can be dropped.
+__global__ void __launch_bounds__(256) k_read_stream(const float4* __restrict__ p, int64_t n4, float* sink) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float acc = 0.f;
+  for (; i + 7 * stride < n4; i += 8 * stride) {
+    float4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+  }
+  for (; i < n4; i += stride) {
+    const float4 v = p[i];
+    acc += (v.x + v.y) + (v.z + v.w);
+  }
+  if (acc != acc) sink[blockIdx.x * 256 + threadIdx.x] = acc;
+}
+
+hipError_t launch_read_stream(const void* p, int64_t bytes, int grid, float* sink, hipStream_t s) {
+  hipLaunchKernelGGL(k_read_stream, dim3((unsigned)grid), dim3(256), 0, s, static_cast<const float4*>(p), bytes / 16,
+                     sink);
   return hipGetLastError();
 }
 

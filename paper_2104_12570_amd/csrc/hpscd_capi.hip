@@ -460,11 +460,12 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
                       : (o->refresh_cols > 0) ? std::max<int64_t>(1, o->refresh_cols / B) : total;
   const bool coop = pl.grid && !(o->flags & HPSCD_F_NO_COOP);
   int refreshes = 0;
-  // bf16 form with the relative-residual rule: the running residual comes
-  // from the bfloat16 columns, so a stop it signals is confirmed on the
-  // residual recomputed from X32 (FP64 sums); if that one is not yet under
-  // the tolerance, the sweeps resume where they stopped.
-  const bool confirm = bf16 && o->refresh_cols > 0 && o->stop == HPSCD_STOP_REL_RESID;
+  // Refreshes with the relative-residual rule: the running residual drifts
+  // from y - X·a (bfloat16 columns, or FP32 rounding over many steps), so a
+  // stop it signals is confirmed on the residual recomputed from X32 (FP64
+  // sums); if that one is not yet under the tolerance, the sweeps resume
+  // where they stopped.
+  const bool confirm = o->refresh_cols > 0 && o->stop == HPSCD_STOP_REL_RESID;
   CtlBlock* hcb = ho.cb;
   bool resumed = false;
   for (int64_t kb = 0; kb < total;) {
@@ -884,6 +885,27 @@ hpscd_status hpscd_select_f32(hpscd_ctx* ctx, int64_t m, int64_t n, const float*
   } catch (...) {
     return fail(HPSCD_ENOMEM, "host allocation failure");
   }
+}
+
+hpscd_status hpscd_read_stream(hpscd_ctx* ctx, const void* buf, int64_t bytes, int32_t passes, double* ms_per_pass,
+                               void* stream) {
+  if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
+  if (!buf || !ms_per_pass) return fail(HPSCD_EINVAL, "NULL argument");
+  if (bytes < 16 || bytes % 16 != 0 || !aligned16(buf))
+    return fail(HPSCD_EINVAL, "need a 16-byte aligned buffer of a positive multiple of 16 bytes");
+  if (passes < 1) return fail(HPSCD_EINVAL, "passes must be >= 1");
+  HIP_TRY(hipSetDevice(ctx->device));
+  const int grid = 8 * ctx->cus;  // eight workgroups of 256 threads per CU
+  hpscd_status rc;
+  if ((rc = ensure(ctx->partial, (size_t)grid * 256 * 4, "sink"))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(launch_read_stream(buf, bytes, grid, ctx->partial.as<float>(), st));  // (first touch)
+  HIP_TRY(hipEventRecord(ctx->ev[0], st));
+  for (int32_t k = 0; k < passes; ++k) HIP_TRY(launch_read_stream(buf, bytes, grid, ctx->partial.as<float>(), st));
+  HIP_TRY(hipEventRecord(ctx->ev[1], st));
+  HIP_TRY(hipEventSynchronize(ctx->ev[1]));
+  *ms_per_pass = elapsed(ctx->ev[0], ctx->ev[1]) / passes;
+  return HPSCD_OK;
 }
 
 hpscd_status hpscd_abort(hpscd_ctx* ctx) {

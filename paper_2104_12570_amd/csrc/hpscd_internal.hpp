@@ -156,5 +156,8 @@ hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s);
+// One pass of 16-byte loads over `bytes` (a multiple of 16) of a buffer; sink:
+// grid*256 floats, written only for a NaN sum.
+hipError_t launch_read_stream(const void* p, int64_t bytes, int grid, float* sink, hipStream_t s);
 
 }  // namespace hpscd

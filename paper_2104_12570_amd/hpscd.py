@@ -94,6 +94,7 @@ _SIGS = {
                                                _dp, _IP, _vp]),
     "hpscd_autotune_batched": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(Sys), _vp, _vp, _OP, _vp, _vp]),
     "hpscd_abort": (ctypes.c_int, [_vp]),
+    "hpscd_read_stream": (ctypes.c_int, [_vp, _vp, _i64, _i32, _dp, _vp]),
     "hpscd_select_f32": (ctypes.c_int, [_vp, _i64, _i64, _vp, _i64, _vp, _vp, _i32, ctypes.c_double, _vp,
                                         ctypes.POINTER(ctypes.c_int32), _dp, _dp, ctypes.POINTER(ctypes.c_int32),
                                         _vp]),
@@ -233,7 +234,7 @@ class Result:
 
 
 def solve(Xt, y, a0=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols=0, block=0, flags=0,
-          team_threads=0, depth=0, want_hist=True, thr=0, order=None) -> Result:
+          team_threads=0, depth=0, want_hist=True, thr=0, order=None, refresh_cols=0) -> Result:
     """Solve X·a = y (Algorithm 1, single precision) on the GPU.
 
     Xt: (n, ldx) float32 CUDA tensor (column j of X in Xt[j, :m]); y: (m,).
@@ -251,7 +252,7 @@ def solve(Xt, y, a0=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols
         if order.dim() != 2 or order.shape[1] != n or order.shape[0] < max_sweeps:
             raise ValueError("order must have shape (>= max_sweeps, n)")
     a = torch.empty(n, dtype=torch.float32, device=Xt.device)
-    opts = make_opts(max_sweeps, stop, tol, check_cols, 0, block, flags, team_threads, depth, thr,
+    opts = make_opts(max_sweeps, stop, tol, check_cols, refresh_cols, block, flags, team_threads, depth, thr,
                      order.data_ptr() if order is not None else 0)
     hist = np.full(max_sweeps + 1, np.nan) if want_hist else None
     info = Info()
@@ -478,6 +479,15 @@ def autotune_batched(Xpool, ypool, table, *, max_sweeps=100, stop=STOP_NONE, tol
     opts = make_opts(max_sweeps, stop, tol)
     _check(_lib.hpscd_autotune_batched(context(Xpool.device.index), len(table), _sys_array(table), _ptr(Xpool),
                                        _ptr(ypool), ctypes.byref(opts), _ptr(a), _stream()))
+
+
+def read_stream_ms(t, passes=10) -> float:
+    """Device milliseconds of one pass of 16-byte loads over the bytes of the
+    CUDA tensor t (the measured read-stream rate of HBM)."""
+    ms = ctypes.c_double()
+    nbytes = t.numel() * t.element_size() // 16 * 16
+    _check(_lib.hpscd_read_stream(context(t.device.index), _ptr(t), nbytes, int(passes), ctypes.byref(ms), _stream()))
+    return ms.value
 
 
 def abort(device: int | None = None):

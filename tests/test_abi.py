@@ -213,3 +213,13 @@ def test_select_rejects_bad_arguments(hp):
                     (dict(tol=float("inf")), "tol"), (dict(tol=-0.5), "tol")):
         assert call(**kw) == hp.EINVAL, kw
         assert msg in hp.last_error(), (kw, hp.last_error())
+
+
+def test_read_stream_rejects_bad_arguments(hp):
+    ms = ctypes.c_double()
+    assert hp._lib.hpscd_read_stream(None, 4096, 1024, 1, ctypes.byref(ms), None) == hp.EINVAL
+    assert hp._lib.hpscd_read_stream(16, 4096, 1000, 1, ctypes.byref(ms), None) == hp.EINVAL
+    assert "multiple of 16" in hp.last_error()
+    assert hp._lib.hpscd_read_stream(16, 4100, 1024, 1, ctypes.byref(ms), None) == hp.EINVAL
+    assert hp._lib.hpscd_read_stream(16, 4096, 1024, 0, ctypes.byref(ms), None) == hp.EINVAL
+    assert "passes" in hp.last_error()

@@ -316,3 +316,22 @@ def test_bf16_wide_kernel_one_workgroup(lib):
     assert r.info["refreshes"] == ref.refreshes
     assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
     assert np.all(np.abs(np.asarray(r.hist) - np.asarray(ref.hist)) <= 1e-5 * ref.hist[0])
+
+
+def test_fp32_confirmed_relative_residual_stop(lib):
+    """Plain single precision with refreshes takes the same FP64-confirmed
+    relative-residual stop as the storage form: the stop lands where the
+    oracle's does (the oracle refreshing from the same FP32 X), and the FP64
+    final check is under tol."""
+    s = gen.wide(m=2000, n=20_000, seed=5)
+    tol, check, refresh = 1e-6, 512, 2048
+    say("fp32 confirmed stop")
+    r = lib.solve(dev(s.Xt), dev(s.y), max_sweeps=3, stop=lib.STOP_REL_RESID, tol=tol, check_cols=check,
+                  refresh_cols=refresh, block=8)
+    ref = oracle.solve(s.Xt, s.y, s.m, max_sweeps=3, stop=oracle.STOP_REL_RESID, tol=tol, check_cols=check,
+                       Xt_refresh=s.Xt, refresh_cols=refresh)
+    say("cols", r.info["cols_done"], ref.cols, "refreshes", r.info["refreshes"], ref.refreshes)
+    assert ref.converged and r.info["converged"] == 1
+    assert r.info["final_rel_resid"] < tol
+    assert r.info["cols_done"] == ref.cols and r.info["refreshes"] == ref.refreshes
+    assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
