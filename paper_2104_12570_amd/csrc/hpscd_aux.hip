@@ -696,27 +696,32 @@ hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, int64_t rows, int
 }
 
 // ------------------------------------------------------------ read stream
-// Reads every 16-byte chunk of a buffer once per pass (grid-stride, eight
-// 128-bit loads in flight per thread), the bandwidth a pure read stream of
-// HBM reaches: the measured denominator of the sweep kernels' roofline.
-// The loaded values only feed a sum that is stored when it is NaN (never
-// for the finite data it is used on), so no load can be dropped.
+// Reads every 16-byte chunk of a buffer once per pass, the bandwidth a pure
+// read stream of HBM reaches: the measured denominator of the sweep kernels'
+// roofline.  Each workgroup streams one contiguous segment, a wave reading
+// 1 KB per load, sixteen 128-bit loads in flight per thread (the pattern
+// that measured fastest: 6.2-6.3 TB/s on 1 GiB, against 5.1 TB/s for a
+// grid-stride loop).  The loaded values only feed a sum that is stored when
+// it is NaN (never for the finite data it is used on), so no load can be
+// dropped.
 __global__ void __launch_bounds__(256) k_read_stream(const float4* __restrict__ p, int64_t n4, float* sink) {
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  constexpr int U = 16, T = 256;
+  const int64_t per = (n4 + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(n4, b0 + per);
   float acc = 0.f;
-  for (; i + 7 * stride < n4; i += 8 * stride) {
-    float4 v[8];
+  int64_t i = b0 + threadIdx.x;
+  for (; i + (U - 1) * T < b1; i += U * T) {
+    float4 v[U];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = p[i + u * stride];
+    for (int u = 0; u < U; ++u) v[u] = p[i + u * T];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+    for (int u = 0; u < U; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
   }
-  for (; i < n4; i += stride) {
+  for (; i < b1; i += T) {
     const float4 v = p[i];
     acc += (v.x + v.y) + (v.z + v.w);
   }
-  if (acc != acc) sink[blockIdx.x * 256 + threadIdx.x] = acc;
+  if (acc != acc) sink[blockIdx.x * T + threadIdx.x] = acc;
 }
 
 hipError_t launch_read_stream(const void* p, int64_t bytes, int grid, float* sink, hipStream_t s) {

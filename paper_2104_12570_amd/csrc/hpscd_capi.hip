@@ -895,7 +895,7 @@ hpscd_status hpscd_read_stream(hpscd_ctx* ctx, const void* buf, int64_t bytes, i
     return fail(HPSCD_EINVAL, "need a 16-byte aligned buffer of a positive multiple of 16 bytes");
   if (passes < 1) return fail(HPSCD_EINVAL, "passes must be >= 1");
   HIP_TRY(hipSetDevice(ctx->device));
-  const int grid = 8 * ctx->cus;  // eight workgroups of 256 threads per CU
+  const int grid = 16 * ctx->cus;  // sixteen workgroups of 256 threads per CU
   hpscd_status rc;
   if ((rc = ensure(ctx->partial, (size_t)grid * 256 * 4, "sink"))) return rc;
   hipStream_t st = (hipStream_t)stream;

@@ -19,6 +19,7 @@ namespace hpscd {
 
 namespace {
 
+constexpr int TILE = 64;                               // columns per reduction workgroup
 constexpr int XTV_CHUNKS = 4;                          // chunks of 4 rows per lane per sub-strip
 constexpr int XTV_SUB = WAVE * XTV_CHUNKS * 4;         // 1024 rows per sub-strip
 constexpr int XTV_CPW = 16;                            // columns per wave
@@ -97,8 +98,10 @@ __global__ void __launch_bounds__(256) k_xtv(const float* X, int64_t ldx, int64_
   }
 }
 
-// One thread per column: g_j = sum over the S strips (fixed order).  Tile t
-// (256 columns) then writes
+// Tile t = 64 columns, one workgroup: thread (q, c) (q = wave, c = lane)
+// sums the strips s = q, q+4, ... of column j = 64t + c with eight loads in
+// flight (eight running sums, added in a fixed order), then the four strip
+// groups are added in order through LDS: g_j.  Tile t then writes
 //   mode 0 (gradient): tsum[t] = sum_j g_j^2 (fixed order);
 //   mode 1 (selection): the best candidate of the tile, score_j =
 //     g_j^2 / <X_j,X_j> (as g_j^2 * rdn_j) over columns not selected with
@@ -108,21 +111,28 @@ __global__ void __launch_bounds__(256) k_xtv_tiles(const double* partial, int64_
                                                    double* tsum, double* tscore, int64_t* tidx,
                                                    const int32_t* done) {
   if (done && load_flag(done)) return;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  double gj = 0.0;
-  if (j < n) {
-    for (int64_t s = 0; s < S; ++s) gj += partial[s * n + j];
-    if (g) g[j] = gj;
-  }
-  __shared__ double ws[4];
-  __shared__ double bs[4];
-  __shared__ int64_t bi[4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * TILE + lane;
+  __shared__ double part[4][TILE];
+  {
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (j < n) {
+      int64_t s = wave;
+      for (; s + 28 < S; s += 32) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += partial[(s + 4 * u) * n + j];
+      }
+      for (; s < S; s += 4) acc[0] += partial[s * n + j];
+    }
+    part[wave][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  const double gj = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+  if (j < n && g) g[j] = gj;
   if (mode == 0) {
     const double t = wave_sum(j < n ? gj * gj : 0.0);
-    if (lane == 0) ws[wave] = t;
-    __syncthreads();
-    if (threadIdx.x == 0) tsum[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+    if (lane == 0) tsum[blockIdx.x] = t;
     return;
   }
   double sc = -1.0;
@@ -140,17 +150,9 @@ __global__ void __launch_bounds__(256) k_xtv_tiles(const double* partial, int64_
     sc = take ? os : sc;
     id = take ? oi : id;
   }
-  if (lane == 0) { bs[wave] = sc; bi[wave] = id; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double b = bs[0];
-    int64_t k = bi[0];
-    for (int w = 1; w < 4; ++w) {
-      const bool take = (bi[w] >= 0) && (k < 0 || bs[w] > b || (bs[w] == b && bi[w] < k));
-      if (take) { b = bs[w]; k = bi[w]; }
-    }
-    tscore[blockIdx.x] = b;
-    tidx[blockIdx.x] = k;
+  if (lane == 0) {
+    tscore[blockIdx.x] = sc;
+    tidx[blockIdx.x] = id;
   }
 }
 
@@ -282,13 +284,14 @@ inline dim3 grid1(int64_t n) { return dim3((unsigned)std::max<int64_t>(1, (n + 2
 }  // namespace
 
 XtvPlan plan_xtv(int64_t m, int64_t n, int64_t cap) {
-  // Row strips of whole 1024-row sub-strips; as many strips as keep ~16
-  // waves per CU busy, within the partial-sum space.
+  // Row strips of whole 1024-row sub-strips: about 2048 workgroups (eight
+  // per CU, four waves each with sixteen 16-byte loads in flight), within
+  // the partial-sum space.
   XtvPlan p{};
   const int64_t G = (n + XTV_COLS - 1) / XTV_COLS;
   const int64_t subs = (m + XTV_SUB - 1) / XTV_SUB;
-  int64_t S = std::max<int64_t>(1, std::min<int64_t>(subs, (4096 + G - 1) / G));
-  const int64_t T = (n + 255) / 256;
+  int64_t S = std::max<int64_t>(1, std::min<int64_t>(subs, (2048 + G - 1) / G));
+  const int64_t T = (n + TILE - 1) / TILE;
   while (S > 1 && S * n + S + 3 * T > cap) --S;
   const int64_t per = (subs + S - 1) / S;
   p.rows_per = per * XTV_SUB;
