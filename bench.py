@@ -190,7 +190,7 @@ def bench_bf16(args):
     y = torch.from_numpy(s.y).cuda()
     Xb = hpscd.convert_bf16(X32)
     tol, check, refresh = 1e-6, 1024, 16384
-    kw = dict(max_sweeps=3, stop=hpscd.STOP_REL_RESID, tol=tol, check_cols=check, refresh_cols=refresh, block=8,
+    kw = dict(max_sweeps=3, stop=hpscd.STOP_REL_RESID, tol=tol, check_cols=check, refresh_cols=refresh,
               want_hist=False)
     steps = max(10, args.steps)
     ms_b, rb = _timed_each(lambda: hpscd.solve_bf16(Xb, X32, y, **kw), steps, args.warmup)
@@ -206,13 +206,13 @@ def bench_bf16(args):
         ref = oracle.solve(s.Xt, s.y, s.m, max_sweeps=k)
         nb = np.linalg.norm(ref.a)
         for name, fn in (("bf16", lambda: hpscd.solve_bf16(Xb, X32, y, max_sweeps=k, refresh_cols=refresh,
-                                                            block=8, want_hist=False)),
-                         ("fp32", lambda: hpscd.solve(X32, y, max_sweeps=k, block=8, want_hist=False))):
+                                                            want_hist=False)),
+                         ("fp32", lambda: hpscd.solve(X32, y, max_sweeps=k, want_hist=False))):
             r = fn()
             equal[f"{name}_sweeps{k}"] = {"rel_err_vs_oracle": float(np.linalg.norm(r.a.cpu().numpy() - ref.a) / nb),
                                           "true_rel_resid": r.info["final_rel_resid"]}
     lit = hpscd.solve_bf16(Xb, X32, y, max_sweeps=3, stop=hpscd.STOP_REL_RESID, tol=tol, check_cols=check,
-                           refresh_cols=10 * s.n, block=8, want_hist=False)
+                           refresh_cols=10 * s.n, want_hist=False)
     cols = ib["cols_done"]
     alg = cols * s.m * 2.0
     sweep_ms = float(np.mean([r.info["sweep_ms"] for r in rb]))

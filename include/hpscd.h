@@ -74,7 +74,8 @@ typedef struct {
   int64_t refresh_cols; /* e = y - X32·a (FP64 sums) every refresh_cols column steps (X32 = X for
                            hpscd_solve_f32); with HPSCD_STOP_REL_RESID a stop signalled by the running
                            residual then holds only if the refreshed one passes too; 0 = never */
-  int32_t block;        /* columns per reduction round (1, 2, 4, 8, or 16 with depth 8); 0 = library choice */
+  int32_t block;        /* columns per reduction round (1, 2, 4, 8; 16 with depth 8 or 9; 32 with depth 9
+                           on bfloat16 columns); 0 = library choice */
   int32_t flags;        /* HPSCD_F_* */
   int32_t team_threads; /* threads per workgroup; 0 = library choice.  Batched calls: 256
                            (four waves, eight chunks per thread) or 512 (eight waves, four) */
@@ -84,7 +85,12 @@ typedef struct {
                            (their rows arrive through LDS); 8: 16-column blocks through each
                            block's precomputed step matrix, no column loads in flight during the
                            exchange (a grid, or one workgroup without exchange for at most 4096
-                           rows) */
+                           rows); 9: the column chain of a short system (at most 2048 rows) on one
+                           workgroup, 16 FP32 or 32 bfloat16 columns per block through its step
+                           matrix, the next block's columns and step matrix in flight (the library
+                           choice for such systems when the options allow it: block 0 or that
+                           size, which divides check_cols, refresh_cols and then n; no thr, no
+                           order, no HPSCD_F_FORCE_GRID) */
   /* Variants of the method (single-system FP32 solves, kernel kind 8 only; the block size is 16): */
   int32_t thr;          /* Section 7, Algorithm 2 (HPSCDP): every sweep takes the columns in consecutive
                            blocks of thr (the last block holds what remains); all columns of a block step

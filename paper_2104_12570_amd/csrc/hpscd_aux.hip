@@ -259,6 +259,14 @@ __global__ void __launch_bounds__(256) k_block_inverse16(const double* rdn, cons
   }
 }
 
+hipError_t launch_colgram_reduce32(const double* partial, int PR, int64_t n, double* rdn, double* gram, int32_t* ctl,
+                                   int64_t* zero_cols, hipStream_t s) {
+  const int64_t nb = (n + 31) / 32, total = nb * (32 * 33 / 2);
+  hipLaunchKernelGGL((k_colgram_reduce<32, false>), dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, partial, PR,
+                     n, rdn, gram, nullptr, ctl, zero_cols, nullptr);
+  return hipGetLastError();
+}
+
 static hipError_t block_inverse16(const double* rdn, const double* gram, int64_t n, double* minv, hipStream_t s,
                                   int32_t thr = 0, const int32_t* done = nullptr) {
   const int64_t nb = (n + 15) / 16;

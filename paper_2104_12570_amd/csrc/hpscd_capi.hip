@@ -156,12 +156,18 @@ hpscd_status validate_opts(const hpscd_opts* o) {
   if (!std::isfinite(o->tol) || o->tol < 0.0) return fail(HPSCD_EINVAL, "tol must be finite and >= 0");
   if (o->check_cols < 0) return fail(HPSCD_EINVAL, "check_cols must be >= 0");
   if (o->refresh_cols < 0) return fail(HPSCD_EINVAL, "refresh_cols must be >= 0");
-  if (o->block != 0 && o->block != 1 && o->block != 2 && o->block != 4 && o->block != 8 && o->block != 16)
-    return fail(HPSCD_EINVAL, "block must be 0, 1, 2, 4, 8 or 16 (got %d)", o->block);
-  if (o->depth != 0 && o->depth != 2 && o->depth != 3 && o->depth != 4 && o->depth != 5 && o->depth != 8)
-    return fail(HPSCD_EINVAL, "depth (kernel kind) must be 0, 2, 3, 4, 5 or 8 (got %d)", o->depth);
-  if (o->block == 16 && o->depth != 0 && o->depth != 8)
-    return fail(HPSCD_EINVAL, "block 16 runs only on the wide-block grid kernel (depth 8)");
+  if (o->block != 0 && o->block != 1 && o->block != 2 && o->block != 4 && o->block != 8 && o->block != 16 &&
+      o->block != 32)
+    return fail(HPSCD_EINVAL, "block must be 0, 1, 2, 4, 8, 16 or 32 (got %d)", o->block);
+  if (o->depth != 0 && o->depth != 2 && o->depth != 3 && o->depth != 4 && o->depth != 5 && o->depth != 8 &&
+      o->depth != 9)
+    return fail(HPSCD_EINVAL, "depth (kernel kind) must be 0, 2, 3, 4, 5, 8 or 9 (got %d)", o->depth);
+  if (o->block == 16 && o->depth != 0 && o->depth != 8 && o->depth != 9)
+    return fail(HPSCD_EINVAL, "block 16 runs only on the wide-block kernel (depth 8) or the chain kernel (depth 9)");
+  if (o->block == 32 && o->depth != 0 && o->depth != 9)
+    return fail(HPSCD_EINVAL, "block 32 runs only on the chain kernel (depth 9)");
+  if (o->depth == 9 && o->block != 0 && o->block != 16 && o->block != 32)
+    return fail(HPSCD_EINVAL, "the chain kernel (depth 9) takes blocks of 16 or 32 columns");
   if ((o->flags & HPSCD_F_FORCE_GRID) && (o->flags & HPSCD_F_FORCE_WG))
     return fail(HPSCD_EINVAL, "FORCE_GRID and FORCE_WG are exclusive");
   if ((int64_t)o->max_sweeps + 1 > (int64_t)1 << 30) return fail(HPSCD_EINVAL, "max_sweeps too large");
@@ -274,7 +280,41 @@ static hpscd_status plan_try(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, cons
               grid ? "grid" : "workgroup", B);
 }
 
-hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, bool bf16, const hpscd_opts* o, Plan* pl) {
+// The column chain on one workgroup (kind 9) for systems of at most 2048
+// rows: 16-column FP32 or 32-column bfloat16 blocks.  Returns false when it
+// does not fit the options (and, when it was asked for, sets the error).
+bool plan_chain(int64_t m, int64_t n, int64_t ldx, bool bf16, const hpscd_opts* o, Plan* pl, hpscd_status* rc) {
+  const bool asked = o->depth == 9 || o->block == 32;
+  *rc = HPSCD_OK;
+  const int B = bf16 ? 32 : 16;
+  const char* why = nullptr;
+  const bool checks = o->check_cols > 0 && o->stop == HPSCD_STOP_REL_RESID;
+  if (m > chain_max_rows()) why = "the chain kernel (depth 9, block 32) holds at most 2048 rows";
+  else if (o->team_threads > 0 && o->team_threads != 512) why = "the chain kernel (depth 9) runs 512 threads";
+  else if ((int64_t)B * ldx * (bf16 ? 2 : 4) > (int64_t)INT32_MAX)
+    why = "the chain kernel (depth 9) addresses a block's columns with 32-bit offsets (ldx too large)";
+  else if (o->flags & HPSCD_F_FORCE_GRID) why = "the chain kernel (depth 9) is one workgroup";
+  else if (o->thr > 1 || o->order) why = "Algorithm 2 and column orders run on the wide-block kernel (depth 8)";
+  else if (o->block > 0 && o->block != B) why = "the chain kernel takes 16 FP32 or 32 bfloat16 columns per block";
+  else if ((checks && o->check_cols % B) || (o->refresh_cols > 0 && o->refresh_cols % B) ||
+           ((checks || o->refresh_cols > 0) && n % B))
+    why = "the chain kernel's block must divide check_cols, refresh_cols and (with either) n";
+  if (why) {
+    if (asked) *rc = fail(HPSCD_EINVAL, "%s", why);
+    return false;
+  }
+  *pl = Plan{false, 512, 1, B, 1, 9, chain_max_rows(), 0};
+  return true;
+}
+
+hpscd_status plan_single(hpscd_ctx* c, int64_t m, int64_t n, int64_t ldx, bool bf16, const hpscd_opts* o, Plan* pl) {
+  // Short systems (one workgroup holds every row): the column chain kernel
+  // by default, unless the options ask for another kernel.
+  if (o->depth == 9 || o->block == 32 || (o->depth == 0 && m <= chain_max_rows())) {
+    hpscd_status rc;
+    if (plan_chain(m, n, ldx, bf16, o, pl, &rc)) return HPSCD_OK;
+    if (rc != HPSCD_OK) return rc;
+  }
   // The wide-block kernel when asked for; by default for FP32 grids, where it
   // measured fastest from 100k to 1M rows (a reduction per 16 columns, none
   // of the exchange's memory operations queued behind column loads), unless
@@ -420,8 +460,14 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   }
   // column statistics (under a column order: before every sweep, below)
   if (!ordered)
-    HIP_TRY(launch_colgram(Xs, bf16, ldxs, m, n, B, w.rdn, w.gram, B == 16 ? w.cross : nullptr, partial, partial_cap,
-                           ctl, &ctl64[C64_ZERO_COLS], st, nullptr, pl.V == 1 ? o->thr : 0));
+  {
+    if (pl.D == 9 && B == 32)
+      HIP_TRY(launch_colgram32(Xs, bf16, ldxs, m, n, w.rdn, w.gram, w.cross, partial, partial_cap, ctl,
+                               &ctl64[C64_ZERO_COLS], st));
+    else
+      HIP_TRY(launch_colgram(Xs, bf16, ldxs, m, n, B, w.rdn, w.gram, B == 16 ? w.cross : nullptr, partial,
+                             partial_cap, ctl, &ctl64[C64_ZERO_COLS], st, nullptr, pl.V == 1 ? o->thr : 0));
+  }
   if (grad_rule)
     HIP_TRY(launch_grad_stop(X32, ldx32, m, n, y, true, 0, o->tol, partial, partial_cap, ctl, ctl64, fstat, w.hist,
                              st));
@@ -434,7 +480,7 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   A.n = n;
   A.rdn = w.rdn;
   A.gram = w.gram;
-  A.minv = B == 16 ? w.cross : nullptr;
+  A.minv = B >= 16 ? w.cross : nullptr;
   A.a64 = w.a64;
   A.e_out = w.eo;
   A.hist = w.hist;
@@ -476,7 +522,8 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
     if (ordered && sweep < o->max_sweeps)
       HIP_TRY(launch_colgram(Xs, false, ldxs, m, n, B, w.rdn, w.gram, w.cross, partial, partial_cap, ctl,
                              sweep == 0 ? &ctl64[C64_ZERO_COLS] : nullptr, st, o->order + sweep * n, 0));
-    HIP_TRY(launch_sweep(pl.T, pl.R, B, bf16, pl.grid, pl.D, A, st, coop, pl.V));
+    if (pl.D == 9) HIP_TRY(launch_chain(bf16, B, A, st));
+    else HIP_TRY(launch_sweep(pl.T, pl.R, B, bf16, pl.grid, pl.D, A, st, coop, pl.V));
     if (grad_rule && A.blk_end < total)
       HIP_TRY(launch_grad_stop(X32, ldx32, m, n, w.eo, false, (int32_t)(sweep + 1), o->tol, partial, partial_cap, ctl,
                                ctl64, fstat, w.hist, st));
@@ -605,7 +652,7 @@ hpscd_status solve_single_ctx(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs
   if (oo.max_sweeps == 0) oo.order = nullptr;  // (no sweep: the order is not read)
   o = &oo;
   Plan pl;
-  hpscd_status rc = plan_single(c, m, n, bf16, o, &pl);
+  hpscd_status rc = plan_single(c, m, n, ldxs, bf16, o, &pl);
   if (rc != HPSCD_OK) return rc;
   HIP_TRY(hipSetDevice(c->device));
   if (pl.V == 2 && n * (int64_t)(ldxs * 4) > (int64_t)0xFFFFFFFF)
@@ -715,7 +762,7 @@ hpscd_status hpscd_solve_f32_noalloc(hpscd_ctx* ctx, int64_t m, int64_t n, const
     hpscd_opts oo = *opts;
     if (oo.max_sweeps == 0) oo.order = nullptr;
     Plan pl;
-    if ((rc = plan_single(ctx, m, n, false, &oo, &pl)) != HPSCD_OK) return rc;
+    if ((rc = plan_single(ctx, m, n, ldx, false, &oo, &pl)) != HPSCD_OK) return rc;
     if (pl.V == 2 && n * (int64_t)(ldx * 4) > (int64_t)0xFFFFFFFF)
       return fail(HPSCD_EINVAL, "a column order needs X below 4 GiB");
     Work w;

@@ -88,6 +88,18 @@ int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid, int D, in
 int sweep_max_workgroups(int T, int R, int B, bool bf16, bool grid, int D, int V = 0);
 bool sweep_variant_exists(int T, int R, int B, bool bf16, bool grid, int D, int V = 0);
 
+// Column chain of a short system on one workgroup (kind 9): 16-column FP32
+// or 32-column bfloat16 blocks through step matrices in SolveArgs::minv.
+bool chain_variant_exists(bool bf16, int B);
+int chain_max_rows();
+hipError_t launch_chain(bool bf16, int B, const SolveArgs& a, hipStream_t s);
+// Reciprocal norms, in-block Gram and step matrices of 32-column blocks.
+hipError_t launch_colgram32(const void* X, bool bf16, int64_t ldx, int64_t m, int64_t n, double* rdn, double* gram,
+                            double* minv, double* partial, int64_t partial_cap, int32_t* ctl, int64_t* zero_cols,
+                            hipStream_t s);
+hipError_t launch_colgram_reduce32(const double* partial, int PR, int64_t n, double* rdn, double* gram, int32_t* ctl,
+                                   int64_t* zero_cols, hipStream_t s);
+
 hipError_t launch_batched(int B, const BatchArgs& a, int grid, hipStream_t s);
 int batched_threads(int code);
 // Batched kernel variants are named by a code: the block size (1, 2 or 4),

@@ -80,7 +80,11 @@ def test_version(hp):
     (dict(tol=float("nan")), "tol"),
     (dict(tol=-1.0), "tol"),
     (dict(block=3), "block"),
-    (dict(block=32), "block"),
+    (dict(block=64), "block"),
+    (dict(block=32, depth=8), "chain kernel"),
+    (dict(block=16, depth=5), "block 16"),
+    (dict(block=8, depth=9), "chain kernel"),
+    (dict(thr=4, depth=9), "wide-block kernel"),
     (dict(flags=2 | 4), "exclusive"),
     (dict(thr=-1), "thr"),
     (dict(thr=4, order=256), "exclusive"),
@@ -109,13 +113,13 @@ def test_validation_accepts(hp):
         assert hp.validate(100, 10, 4096, 100, 4, 64, hp.make_opts(5, **kw), 128) == hp.OK, kw
 
 
-@pytest.mark.parametrize("depth", [0, 2, 3, 4, 5, 8])
+@pytest.mark.parametrize("depth", [0, 2, 3, 4, 5, 8, 9])
 def test_kernel_kinds_accepted(hp, depth):
     o = hp.make_opts(5, depth=depth)
     assert hp.validate(100, 10, 4096, 100, 4, 64, o, 128) == hp.OK
 
 
-@pytest.mark.parametrize("depth", [1, 6, 7, 9, 11, 12, 13, 14, -1])
+@pytest.mark.parametrize("depth", [1, 6, 7, 10, 11, 12, 13, 14, -1])
 def test_unknown_kernel_kind_rejected(hp, depth):
     o = hp.make_opts(5, depth=depth)
     assert hp.validate(100, 10, 4096, 100, 4, 64, o, 128) == hp.EINVAL
