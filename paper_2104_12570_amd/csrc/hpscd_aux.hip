@@ -152,24 +152,36 @@ __global__ void __launch_bounds__(256) k_colgram16_mfma(const void* X, int64_t l
   }
 }
 
-// Sum the PR partials (fixed order, one wave per output) into rdn[nb*B],
-// gram[nb*NG] and (CROSS) cross[nb*B*B].
-template <int B, bool CROSS>
+// Sum the PR partials (fixed order) into rdn[nb*B], gram[nb*NG] and (CROSS)
+// cross[nb*B*B].  WAVE: one wave per output, its lanes striding over the
+// partials (many partials: tall systems); else one thread per output adding
+// them in turn (a few partials: short, wide systems with many blocks).
+template <int B, bool CROSS, bool WAVE>
 __global__ void __launch_bounds__(256) k_colgram_reduce(const double* partial, int PR, int64_t n, double* rdn,
                                                         double* gram, double* cross, int32_t* ctl,
                                                         int64_t* zero_cols, const int32_t* done) {
   constexpr int NP = B * (B + 1) / 2, NG = B * (B - 1) / 2, NX = CROSS ? B * B : 0, NPX = NP + NX;
   if (done && load_flag(done)) return;
-  const int lane = threadIdx.x & 63;
   const int64_t nb = (n + B - 1) / B;
-  const int64_t idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (idx >= nb * NPX) return;
+  int64_t idx;
+  double s = 0.0;
+  if constexpr (WAVE) {
+    const int lane = threadIdx.x & 63;
+    idx = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (idx >= nb * NPX) return;
+    const int64_t b = idx / NPX;
+    const int q = (int)(idx % NPX);
+    double acc = 0.0;
+    for (int r = lane; r < PR; r += 64) acc += partial[((int64_t)r * nb + b) * NPX + q];
+    s = wave_sum(acc);
+    if (lane != 0) return;
+  } else {
+    idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= nb * NPX) return;
+    for (int r = 0; r < PR; ++r) s += partial[(int64_t)r * nb * NPX + idx];
+  }
   const int64_t b = idx / NPX;
   const int q = (int)(idx % NPX);
-  double acc = 0.0;
-  for (int r = lane; r < PR; r += 64) acc += partial[((int64_t)r * nb + b) * NPX + q];
-  const double s = wave_sum(acc);
-  if (lane != 0) return;
   if (q >= NP) {
     cross[b * NX + (q - NP)] = s;
     return;
@@ -189,6 +201,20 @@ __global__ void __launch_bounds__(256) k_colgram_reduce(const double* partial, i
   } else {
     gram[b * NG + l * (l - 1) / 2 + i] = (j < n) ? s : 0.0;
   }
+}
+
+template <int B, bool CROSS>
+static void launch_colgram_reduce(const double* partial, int PR, int64_t n, double* rdn, double* gram,
+                                  double* cross, int32_t* ctl, int64_t* zero_cols, const int32_t* done,
+                                  hipStream_t s) {
+  constexpr int NPX = B * (B + 1) / 2 + (CROSS ? B * B : 0);
+  const int64_t total = (n + B - 1) / B * NPX;
+  if (PR > 16)
+    hipLaunchKernelGGL((k_colgram_reduce<B, CROSS, true>), dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s,
+                       partial, PR, n, rdn, gram, cross, ctl, zero_cols, done);
+  else
+    hipLaunchKernelGGL((k_colgram_reduce<B, CROSS, false>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       s, partial, PR, n, rdn, gram, cross, ctl, zero_cols, done);
 }
 
 // Tables of 16-column blocks from those of 8-column blocks: the strictly
@@ -261,9 +287,7 @@ __global__ void __launch_bounds__(256) k_block_inverse16(const double* rdn, cons
 
 hipError_t launch_colgram_reduce32(const double* partial, int PR, int64_t n, double* rdn, double* gram, int32_t* ctl,
                                    int64_t* zero_cols, hipStream_t s) {
-  const int64_t nb = (n + 31) / 32, total = nb * (32 * 33 / 2);
-  hipLaunchKernelGGL((k_colgram_reduce<32, false>), dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, partial, PR,
-                     n, rdn, gram, nullptr, ctl, zero_cols, nullptr);
+  launch_colgram_reduce<32, false>(partial, PR, n, rdn, gram, nullptr, ctl, zero_cols, nullptr, s);
   return hipGetLastError();
 }
 
@@ -300,9 +324,7 @@ static hipError_t colgram_impl(const void* X, int64_t ldx, int64_t m, int64_t n,
                      rows_per, partial);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  const int64_t total = nb * NPX;
-  hipLaunchKernelGGL((k_colgram_reduce<B, CROSS>), dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, partial,
-                     (int)PR, n, rdn, gram, cross, ctl, zero_cols, nullptr);
+  launch_colgram_reduce<B, CROSS>(partial, (int)PR, n, rdn, gram, cross, ctl, zero_cols, nullptr, s);
   return hipGetLastError();
 }
 
@@ -328,9 +350,7 @@ static hipError_t colgram16_mfma(const void* X, int64_t ldx, int64_t m, int64_t 
                      rows_per, partial, map, done);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  const int64_t total = nb * NPX;
-  hipLaunchKernelGGL((k_colgram_reduce<B, false>), dim3((unsigned)((total + 3) / 4)), dim3(256), 0, s, partial,
-                     (int)PR, n, rdn, gram, nullptr, ctl, zero_cols, done);
+  launch_colgram_reduce<B, false>(partial, (int)PR, n, rdn, gram, nullptr, ctl, zero_cols, done, s);
   return hipGetLastError();
 }
 
@@ -515,8 +535,11 @@ __global__ void __launch_bounds__(256) k_resid_rows(const float* X, int64_t ldx,
 }
 
 // Wide layout: workgroup g accumulates X[:, cols of g]·a for a tile of rows
-// into partial[g*m_tile + row] (FP64); k_resid_cols_reduce adds the partials.
+// into partial[g*tile + row] (FP64, columns in order); k_resid_cols_reduce
+// adds the partials.  RC_U columns are requested before their products are
+// added, so a thread keeps RC_U * RC_CHUNKS 16-byte loads in flight.
 constexpr int RC_CHUNKS = 2;  // chunks per thread per row tile: 2048 rows per tile
+constexpr int RC_U = 8;
 __global__ void __launch_bounds__(256) k_resid_cols(const float* X, int64_t ldx, int64_t m, int64_t row0,
                                                     int64_t ncols, int64_t cols_per, const double* a64,
                                                     const float* a32, double* partial, int64_t tile,
@@ -532,20 +555,34 @@ __global__ void __launch_bounds__(256) k_resid_cols(const float* X, int64_t ldx,
     lim[q] = rr[q] < m ? (int)min((int64_t)4, m - rr[q]) : 0;
     for (int i = 0; i < 4; ++i) acc[q][i] = 0.0;
   }
-  for (int64_t j = c0; j < c1; ++j) {
-    const double aj = a64 ? a64[j] : (a32 ? (double)a32[j] : 0.0);
-    if (aj == 0.0) continue;
+  auto coef = [&](int64_t j) { return a64 ? a64[j] : (a32 ? (double)a32[j] : 0.0); };
+  auto add = [&](const float4 (&x)[RC_CHUNKS], double aj) {
 #pragma unroll
     for (int q = 0; q < RC_CHUNKS; ++q) {
-      if (lim[q] > 0) {
-        float4 x = load_chunk<F32>(X, j * ldx + rr[q]);
-        if (lim[q] < 4) x = mask_chunk<F32>(x, lim[q]);
-        acc[q][0] = fma((double)x.x, aj, acc[q][0]);
-        acc[q][1] = fma((double)x.y, aj, acc[q][1]);
-        acc[q][2] = fma((double)x.z, aj, acc[q][2]);
-        acc[q][3] = fma((double)x.w, aj, acc[q][3]);
-      }
+      const float4 v = lim[q] < 4 ? mask_chunk<F32>(x[q], lim[q]) : x[q];
+      acc[q][0] = fma((double)v.x, aj, acc[q][0]);
+      acc[q][1] = fma((double)v.y, aj, acc[q][1]);
+      acc[q][2] = fma((double)v.z, aj, acc[q][2]);
+      acc[q][3] = fma((double)v.w, aj, acc[q][3]);
     }
+  };
+  int64_t j = c0;
+  for (; j + RC_U <= c1; j += RC_U) {
+    float4 x[RC_U][RC_CHUNKS];
+#pragma unroll
+    for (int u = 0; u < RC_U; ++u)
+#pragma unroll
+      for (int q = 0; q < RC_CHUNKS; ++q)
+        x[u][q] = lim[q] > 0 ? load_chunk<F32>(X, (j + u) * ldx + rr[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int u = 0; u < RC_U; ++u) add(x[u], coef(j + u));
+  }
+  for (; j < c1; ++j) {
+    float4 x[RC_CHUNKS];
+#pragma unroll
+    for (int q = 0; q < RC_CHUNKS; ++q)
+      x[q] = lim[q] > 0 ? load_chunk<F32>(X, j * ldx + rr[q]) : make_float4(0.f, 0.f, 0.f, 0.f);
+    add(x, coef(j));
   }
 #pragma unroll
   for (int q = 0; q < RC_CHUNKS; ++q)
@@ -555,24 +592,44 @@ __global__ void __launch_bounds__(256) k_resid_cols(const float* X, int64_t ldx,
     }
 }
 
-__global__ void k_resid_cols_reduce(const double* partial, int G, int64_t tile, int64_t row0, int64_t m,
-                                    const float* y, float* e_out, double* sq_partial,
-                                    const int32_t* skip_if, double* e64_out) {
+// Rows of a tile, 64 per workgroup (lane = row): y_r minus the sum of the G
+// partials, wave w adding those of g in [w*GQ, (w+1)*GQ) in order (eight
+// loads in flight), the four wave sums then added in order; writes e (FP32
+// and/or FP64) and the workgroup's sum of squares.
+__global__ void __launch_bounds__(256) k_resid_cols_reduce(const double* partial, int G, int64_t tile, int64_t row0,
+                                                           int64_t m, const float* y, float* e_out,
+                                                           double* sq_partial, const int32_t* skip_if,
+                                                           double* e64_out) {
   if (skip_if && *skip_if) return;
-  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+  const int GQ = (G + 3) / 4;
+  const int g0 = w * GQ, g1 = min(G, g0 + GQ);
+  double s = 0.0;
+  if (r < tile) {
+    int g = g0;
+    for (; g + 8 <= g1; g += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(g + u) * tile + r];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; g < g1; ++g) s += partial[(int64_t)g * tile + r];
+  }
+  __shared__ double ws[4][64];
+  ws[w][lane] = s;
+  __syncthreads();
+  if (w != 0) return;
   double v = 0.0;
   if (r < tile && row0 + r < m) {
-    double s = 0.0;
-    for (int g = 0; g < G; ++g) s += partial[(int64_t)g * tile + r];
-    v = (double)y[row0 + r] - s;
+    const double tot = ((ws[0][lane] + ws[1][lane]) + ws[2][lane]) + ws[3][lane];
+    v = (double)y[row0 + r] - tot;
     if (e_out) e_out[row0 + r] = (float)v;
     if (e64_out) e64_out[row0 + r] = v;
   }
-  __shared__ double wsum[4];
-  double sq = wave_sum(v * v);
-  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = sq;
-  __syncthreads();
-  if (threadIdx.x == 0) sq_partial[blockIdx.x] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+  const double sq = wave_sum(v * v);
+  if (lane == 0) sq_partial[blockIdx.x] = sq;
 }
 
 // Fixed-order sum of `count` doubles into *out (single workgroup).
@@ -604,10 +661,11 @@ hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t ncols
     if (norm2) hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(256), 0, s, partial, G, norm2, 0, skip_if);
     return hipGetLastError();
   }
-  // Column-split form for short, wide systems.
+  // Column-split form for short, wide systems: up to 256 workgroups of at
+  // least 32 columns each.
   const int64_t tile = 256 * RC_CHUNKS * 4;
-  int64_t G = std::min<int64_t>(1024, std::max<int64_t>(1, ncols / 64));
-  const int64_t sqn = (tile + 255) / 256;
+  int64_t G = std::min<int64_t>(256, std::max<int64_t>(1, ncols / 32));
+  const int64_t sqn = (tile + 63) / 64;
   while (G > 1 && G * tile + sqn * ((m + tile - 1) / tile) > partial_cap) G /= 2;
   const int64_t cols_per = (ncols + G - 1) / G;
   G = (ncols + cols_per - 1) / cols_per;

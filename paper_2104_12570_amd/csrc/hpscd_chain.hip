@@ -11,15 +11,17 @@
 //  * all 512 threads hold 4 rows each (2048 rows), so a 2000-row system
 //    keeps every thread busy: a column is one 16-byte (FP32) or 8-byte
 //    (bfloat16) load per thread;
-//  * the next block's columns are in flight while the current one is
-//    reduced (a ring of two register blocks, every load unconditional);
+//  * the columns of the next two blocks are in flight while the current one
+//    is reduced (a ring of three register blocks, every load unconditional):
+//    a lone workgroup's loads take longer than one block's arithmetic;
 //  * the block is as wide as the registers allow: 16 FP32 columns or 32
-//    bfloat16 columns (the same 128 registers for the ring) -- halving the
+//    bfloat16 columns (the same registers for the ring) -- halving the
 //    bytes halves a block's register footprint, so the storage form takes
 //    half as many reductions per sweep;
 //  * the step matrix of the next block is staged in LDS (double buffer) by
-//    all threads; wave 0 computes da and the stop tests; one barrier after
-//    the partial sums, one after da.
+//    all threads; after the partial sums every wave computes four rows of
+//    da = M g (16 lanes a row), wave 0 also the stop tests; one barrier
+//    after the partial sums, one after da.
 #include "hpscd_device.hpp"
 #include "hpscd_internal.hpp"
 
@@ -126,22 +128,31 @@ __global__ void __launch_bounds__(CT) k_sweep_chain(SolveArgs A) {
   // step-matrix rows and columns are zero, and it stays inside X)
   const int64_t col_bytes = A.ldx * (int64_t)Q::BYTES;
   const int voff = (int)(roff * Q::BYTES);
-  auto load_block = [&](raw (&xb)[B], int b) {
+  struct BlockRef {
+    __amdgpu_buffer_rsrc_t rs;
+    int nvalid;
+  };
+  auto block_ref = [&](int b) {
     b = __builtin_amdgcn_readfirstlane(b);
     const int64_t j0 = (int64_t)b * B;
     const int nvalid = n - j0 < B ? (int)(n - j0) : B;
     const uint32_t nrec = (uint32_t)((int64_t)nvalid * col_bytes);  // (< 2^32: B * col_bytes is checked by the host)
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<char*>(reinterpret_cast<const char*>(A.X) + j0 * col_bytes), 0, (int)nrec, 0x00020000);
-#pragma unroll
-    for (int l = 0; l < B; ++l) {
-      const int lc = l < nvalid ? l : nvalid - 1;
-      xb[l] = Q::load(rs, voff, (int)(lc * col_bytes));
-    }
+    return BlockRef{__builtin_amdgcn_make_buffer_rsrc(
+                        const_cast<char*>(reinterpret_cast<const char*>(A.X) + j0 * col_bytes), 0, (int)nrec,
+                        0x00020000),
+                    nvalid};
   };
-  // the step matrix of block b: B*B doubles, two per thread (B = 32) or
-  // two per thread of the first B*B/2 threads (B = 16)
-  constexpr int MPT = (B * B + CT - 1) / CT;  // doubles per thread (2 for B = 32, 1 for 16)
+  auto load_col = [&](const BlockRef& r, int l) {
+    const int lc = l < r.nvalid ? l : r.nvalid - 1;
+    return Q::load(r.rs, voff, (int)(lc * col_bytes));
+  };
+  auto load_block = [&](raw (&xb)[B], int b) {
+    const BlockRef r = block_ref(b);
+#pragma unroll
+    for (int l = 0; l < B; ++l) xb[l] = load_col(r, l);
+  };
+  // the step matrix of block b: B*B doubles, MPT per thread
+  constexpr int MPT = (B * B + CT - 1) / CT;  // (2 for B = 32, 1 for 16)
   auto load_m = [&](double (&mv)[MPT], int b) {
 #pragma unroll
     for (int k = 0; k < MPT; ++k) {
@@ -156,19 +167,32 @@ __global__ void __launch_bounds__(CT) k_sweep_chain(SolveArgs A) {
       if (idx < B * B) msh[buf][idx] = mv[k];
     }
   };
+  // block index k blocks after b (k small, wave-uniform)
+  auto adv = [&](int b, int k) {
+    b += k;
+    while (b >= nb) b -= nb;
+    return b;
+  };
 
-  raw x0[B], x1[B];
-  double mv[MPT];
-  // prologue: the first block's step matrix to LDS, its columns and the
-  // next block's in flight
-  load_m(mv, bi);
-  store_m(mv, 0);
-  load_block(x0, bi);
+  // A ring of three register blocks.  Step t (block t in slot t mod 3)
+  // requests block t + 2 into the slot that block t - 1 has just left,
+  // spread over its dot products (one column load between the arithmetic of
+  // two columns, so the memory pipeline works while the ALUs do); its step
+  // matrix M(t + 3) goes into the register slot whose matrix was staged in
+  // LDS at the end of step t - 1, and M(t + 1) is staged at the end of
+  // step t.
+  constexpr int NR = 3;
+  raw xr[NR][B];
+  double mr[NR][MPT];
   {
-    const int b1 = bi + 1 == nb ? 0 : bi + 1;
-    load_m(mv, b1);
-    load_block(x1, b1);
+    double m0[MPT];
+    load_m(m0, bi);
+    store_m(m0, 0);
   }
+  load_m(mr[1], adv(bi, 1));
+  load_block(xr[0], bi);
+  load_m(mr[2], adv(bi, 2));
+  load_block(xr[1], adv(bi, 1));
   int mcur = 0;
 
   auto finalize = [&](int sd, bool conv, int64_t cols, double nrm2) {
@@ -180,11 +204,20 @@ __global__ void __launch_bounds__(CT) k_sweep_chain(SolveArgs A) {
     K->fstat[0] = nrm2;
   };
 
-  // One block on the ring buffer x (the current block; the next one is in
-  // flight in the other buffer).  Returns true when the solve stops.
-  auto step = [&](raw(&x)[B]) -> bool {
+  // da of the block is shared out as 16 lanes per row of M, four rows per
+  // wave (waves 0 .. B/4 - 1); each lane takes B/16 entries of its row
+  constexpr int QL = B / 16;
+  const int mrow = 4 * wave + (lane >> 4);
+  const int q0 = (lane & 15) * QL;
+  const bool owns = wave < B / 4 && (lane & 15) == 0;
+
+  // One block on the ring buffer x (which holds block bi); mnext holds the
+  // step matrix of the next block.  Returns true when the solve stops.
+  auto step = [&](raw(&x)[B], raw(&xfree)[B], double(&mload)[MPT], double(&mnext)[MPT]) -> bool {
     bi = __builtin_amdgcn_readfirstlane(bi);
     const int64_t j0 = (int64_t)bi * B;
+    load_m(mload, adv(bi, 3));
+    const BlockRef ahead = block_ref(adv(bi, 2));
     // partial sums of this thread's rows: the B dots and ||e||^2
     {
       if (straddle) {
@@ -202,6 +235,8 @@ __global__ void __launch_bounds__(CT) k_sweep_chain(SolveArgs A) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) acc = fmaf(Q::get(x[16 * h + l], i), e[i], acc);
           p[l] = acc;
+          xfree[16 * h + l] = load_col(ahead, 16 * h + l);
+          __builtin_amdgcn_sched_barrier(0);
         }
         const float t = wave_sum16_scatter(p);
         if ((lane & 3) == 0) red[wave][16 * h + (lane >> 2)] = t;
@@ -213,15 +248,31 @@ __global__ void __launch_bounds__(CT) k_sweep_chain(SolveArgs A) {
       if (lane == 0) red[wave][B] = tn;
     }
     chain_barrier();
-    // wave 0: totals (FP64, fixed order), stop tests, da = M g
-    if (wave == 0) {
-      double g = 0.0;
-      if (lane < NV) {
+    // da = M g: the totals g_q (FP64, fixed order) a lane needs, its terms
+    // of row mrow, and the row's sum over its 16 lanes
+    double da = 0.0;
+    if (wave < B / 4) {
+      double part = 0.0;
 #pragma unroll
-        for (int w = 0; w < CNW; ++w) g += (double)red[w][lane];
+      for (int u = 0; u < QL; ++u) {
+        double gq = 0.0;
+#pragma unroll
+        for (int w = 0; w < CNW; ++w) gq += (double)red[w][q0 + u];
+        part = fma(msh[mcur][mrow * B + q0 + u], gq, part);
       }
-      const double nrm2 = readlane_f64(g, B);
-      int stop = 0;  // 1: stop before this block, 2: non-finite
+      part += dpp_f64<0xB1>(part);   // quad_perm [1,0,3,2]
+      part += dpp_f64<0x4E>(part);   // quad_perm [2,3,0,1]
+      part += dpp_f64<0x141>(part);  // row_half_mirror
+      part += dpp_f64<0x140>(part);  // row_mirror: every lane of the row holds the sum
+      da = part;
+      if ((lane & 15) == 0) dash[mrow] = (float)part;
+    }
+    // wave 0: ||e||^2 and the stop tests
+    if (wave == 0) {
+      double nrm2 = 0.0;
+#pragma unroll
+      for (int w = 0; w < CNW; ++w) nrm2 += (double)red[w][B];
+      int stop = 0;  // 1: stop before this block, 2: non-finite, 3: aborted
       if (!(nrm2 <= DBL_MAX)) {
         stop = 2;
       } else if (bi == 0) {
@@ -253,21 +304,14 @@ __global__ void __launch_bounds__(CT) k_sweep_chain(SolveArgs A) {
         store_flag(&K->ctl[CTL_ERR], stop == 3 ? ERR_ABORTED : ERR_NONFINITE);
         finalize(sdone, false, (int64_t)sdone * n + j0, nrm2);
       }
-      if (lane < B) {
-        double dl = 0.0;
-        const double* mr = &msh[mcur][lane * B];
-#pragma unroll
-        for (int q = 0; q < B; ++q) dl = fma(mr[q], readlane_f64(g, q), dl);
-        dash[lane] = (float)dl;
-        // (an atomic add without return: no load to wait for, which would
-        // also wait for the next block's columns in flight)
-        if (!stop && j0 + lane < n)
-          (void)__hip_atomic_fetch_add(&A.a64[j0 + lane], dl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
       if (lane == 0) flag = stop;
     }
     chain_barrier();
     if (flag) return true;
+    // (an atomic add without return: no load to wait for, which would also
+    // wait for the columns in flight)
+    if (owns && j0 + mrow < n)
+      (void)__hip_atomic_fetch_add(&A.a64[j0 + mrow], da, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // the axpy with the block's B steps
 #pragma unroll
     for (int l = 0; l < B; ++l) Q::refresh(x[l]);
@@ -281,24 +325,19 @@ __global__ void __launch_bounds__(CT) k_sweep_chain(SolveArgs A) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) e[i] = i < lim ? e[i] : 0.f;
     }
-    // next: stage the next block's step matrix (requested before the next
-    // block's columns, so waiting for it leaves those in flight), then
-    // request the block after it into the registers just freed, its step
-    // matrix first
-    const int bn = bi + 1 == nb ? 0 : bi + 1;
-    const int bnn = bn + 1 == nb ? 0 : bn + 1;
-    store_m(mv, mcur ^ 1);
-    load_m(mv, bnn);
-    load_block(x, bnn);
+    // next: stage the next block's step matrix
+    store_m(mnext, mcur ^ 1);
     mcur ^= 1;
-    bi = bn;
+    bi = adv(bi, 1);
     if (bi == 0) ++sdone;
     return false;
   };
-  // (two steps per iteration, so each ring buffer is a fixed register array)
-  for (int64_t k = 0; k < nblocks; k += 2) {
-    if (step(x0)) break;
-    if (k + 1 >= nblocks || step(x1)) break;
+  // (NR steps per iteration, so each ring buffer is a fixed register array)
+  static_assert(NR == 3, "the loop below is written for a ring of three");
+  for (int64_t k = 0; k < nblocks; k += NR) {
+    if (step(xr[0], xr[2], mr[0], mr[1])) break;
+    if (k + 1 >= nblocks || step(xr[1], xr[0], mr[1], mr[2])) break;
+    if (k + 2 >= nblocks || step(xr[2], xr[1], mr[2], mr[0])) break;
   }
   for (int i = 0; i < 4; ++i)
     if (i < lim) A.e_out[r0 + i] = e[i];
