@@ -224,9 +224,12 @@ hpscd_status hpscd_solve_batched_f32(hpscd_ctx* ctx, int32_t count, const hpscd_
                                      double* final_rel_resid, hpscd_info* info, void* stream);
 
 /* Time the batched kernel's variants on this batch (block size 1, 2 or 4;
- * systems that fit one wave packed four to a workgroup, or one workgroup per
- * system) and remember the fastest for batches of the same shape (kept in the
- * context). */
+ * systems that fit one wave packed as many to a workgroup as it has waves, or
+ * one workgroup per system) and remember the fastest for batches of the same
+ * shape (kept in the context), together with the sweeps each system took:
+ * later solves and plans of such a batch hand out the systems in decreasing
+ * order of (sweeps + 1) * blocks * the team's time per block, so the longest
+ * column chains start first.  The order changes no result. */
 hpscd_status hpscd_autotune_batched(hpscd_ctx* ctx, int32_t count, const hpscd_sys* sys, const float* Xpool,
                                     const float* ypool, const hpscd_opts* opts, float* apool, void* stream);
 

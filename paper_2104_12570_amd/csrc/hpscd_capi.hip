@@ -79,7 +79,8 @@ constexpr uint64_t kTimeoutTicks = 1000000000ull;  // 10 s of the 100 MHz clock
 
 struct Tuned {
   int B;
-  int64_t wave_max_m;  // systems with m <= this share a workgroup, one per wave
+  int64_t wave_max_m;            // systems with m <= this share a workgroup, one per wave
+  std::vector<int32_t> sweeps;   // sweeps each system took when tuned (order hint; empty: none)
 };
 
 // Device workspace of one batched solve (the context's, or a plan's own).
@@ -996,11 +997,18 @@ hpscd_status validate_batch(int32_t count, const hpscd_sys* sys, const float* Xp
 }
 
 // Work items in longest-processing-time order: systems that fit one wave are
-// grouped as many to an item as the workgroup has waves, by decreasing size;
+// grouped as many to an item as the workgroup has waves, by decreasing cost;
 // larger systems get a whole workgroup.  The queue hands items out in this
 // order.  `code` names the kernel variant (block size and shape).
+//
+// Cost model: a team's time per block is a latency, nearly independent of
+// the rows (measured on the 4096-system batch: about 1.5 us for a one-wave
+// team, 2.7 us for a workgroup, over 256 to 8192 rows), so a system costs
+// (sweeps + 1) * blocks * t_team.  `sweeps` (optional) are the sweep counts
+// the systems took when the batch was tuned; without them every system
+// counts one sweep.  Item cost: that of its costliest system.
 void plan_batch(int32_t count, const hpscd_sys* sys, int code, int64_t wave_max_m, int hist_len, double tol,
-                BatchPlan* bp) {
+                const std::vector<int32_t>& sweeps, BatchPlan* bp) {
   const int B = batched_block(code);
   bp->sd.resize(count);
   bp->blk_first.resize(count);
@@ -1021,17 +1029,21 @@ void plan_batch(int32_t count, const hpscd_sys* sys, int code, int64_t wave_max_
   std::vector<int32_t> small, big;
   const int64_t wave_rows = std::min<int64_t>(wave_max_m, batched_rows_per_wave(code));
   for (int32_t i = 0; i < count; ++i) (sys[i].m <= wave_rows ? small : big).push_back(i);
-  auto work = [&](int32_t i) { return (double)sys[i].m * (double)sys[i].n; };
-  auto by_work = [&](int32_t a, int32_t b) { return work(a) > work(b); };
-  std::sort(small.begin(), small.end(), by_work);
-  std::sort(big.begin(), big.end(), by_work);
+  const bool hint = (int32_t)sweeps.size() == count;
+  auto cost = [&](int32_t i, bool wave_team) {
+    const double nbi = (double)((sys[i].n + B - 1) / B);
+    const double sw = hint ? (double)sweeps[i] + 1.0 : 1.0;
+    return sw * nbi * (wave_team ? 1.5 : 2.7) + 1e-9 * (double)sys[i].m;  // (ties: larger first)
+  };
+  std::sort(small.begin(), small.end(), [&](int32_t a, int32_t b) { return cost(a, true) > cost(b, true); });
+  std::sort(big.begin(), big.end(), [&](int32_t a, int32_t b) { return cost(a, false) > cost(b, false); });
   std::vector<std::pair<double, WorkItem>> items;
-  for (int32_t i : big) items.push_back({work(i), WorkItem{0, 1, {i}}});
+  for (int32_t i : big) items.push_back({cost(i, false), WorkItem{0, 1, {i}}});
   const int per = std::min<int>(batched_threads(code) / WAVE, (int)(sizeof(WorkItem::sys) / sizeof(int32_t)));
   for (size_t k = 0; k < small.size(); k += per) {
     WorkItem w{1, 0, {}};
     for (int q = 0; q < per && k + q < small.size(); ++q) w.sys[w.count++] = small[k + q];
-    items.push_back({work(small[k]), w});
+    items.push_back({cost(small[k], true), w});
   }
   std::stable_sort(items.begin(), items.end(), [](auto& a, auto& b) { return a.first > b.first; });
   bp->items.clear();
@@ -1059,12 +1071,12 @@ struct BatchLayout {
 // Plan the batch, size the workspace, and upload the tables (waits for the
 // upload: the staging buffer is the context's pinned buffer).
 hpscd_status prepare_batch(hpscd_ctx* c, BatchWork& w, int32_t count, const hpscd_sys* sys, bool has_a0,
-                           const hpscd_opts* o, int B, int64_t wave_max_m, BatchPlan& bp, BatchLayout& L,
-                           hipStream_t st) {
+                           const hpscd_opts* o, int B, int64_t wave_max_m, const std::vector<int32_t>& sweeps,
+                           BatchPlan& bp, BatchLayout& L, hipStream_t st) {
   HIP_TRY(hipSetDevice(c->device));
   L.count = count;
   L.hist_len = o->max_sweeps + 1;
-  plan_batch(count, sys, B, wave_max_m, L.hist_len, o->tol, &bp);
+  plan_batch(count, sys, B, wave_max_m, L.hist_len, o->tol, sweeps, &bp);
   L.sys_bytes = bp.sd.size() * sizeof(SysDesc);
   L.item_bytes = bp.items.size() * sizeof(WorkItem);
   L.blk_bytes = bp.blk_first.size() * sizeof(int64_t);
@@ -1205,12 +1217,12 @@ int batched_grid(hpscd_ctx* c, const BatchPlan& bp, int B) {
 }
 
 hpscd_status solve_batched(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, const float* Xpool, const float* ypool,
-                           const float* a0pool, const hpscd_opts* o, int B, int64_t wave_max_m, float* apool,
-                           double* hist, int32_t* sweeps_done, int32_t* converged, double* final_rel,
-                           hpscd_info* info, hipStream_t st) {
+                           const float* a0pool, const hpscd_opts* o, int B, int64_t wave_max_m,
+                           const std::vector<int32_t>& hint, float* apool, double* hist, int32_t* sweeps_done,
+                           int32_t* converged, double* final_rel, hpscd_info* info, hipStream_t st) {
   BatchPlan bp;
   BatchLayout L;
-  hpscd_status rc = prepare_batch(c, c->bw, count, sys, a0pool != nullptr, o, B, wave_max_m, bp, L, st);
+  hpscd_status rc = prepare_batch(c, c->bw, count, sys, a0pool != nullptr, o, B, wave_max_m, hint, bp, L, st);
   if (rc != HPSCD_OK) return rc;
   if ((rc = enqueue_batch(c, c->bw, bp, L, Xpool, ypool, a0pool, o, B, apool, c->ev, st)) != HPSCD_OK) return rc;
   return collect_batch(c, c->bw, L, sys, !(o->flags & HPSCD_F_NO_FINAL_CHECK), B, batched_grid(c, bp, B), hist,
@@ -1219,7 +1231,7 @@ hpscd_status solve_batched(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, co
 
 Tuned batched_choice(hpscd_ctx* c, int32_t count, const hpscd_sys* sys, const hpscd_opts* o) {
   auto it = c->tuned.find(batch_key(count, sys));
-  Tuned t = it != c->tuned.end() ? it->second : Tuned{1, batched_rows_per_wave(1)};
+  Tuned t = it != c->tuned.end() ? it->second : Tuned{1, batched_rows_per_wave(1), {}};
   if (o->block > 0) t.B = o->block + (t.B & kBatchWide);  // (the tuned shape stays)
   // team_threads asks for a workgroup shape: 256 (four waves) or 512 (eight)
   if (o->team_threads == 256) t.B = batched_block(t.B);
@@ -1241,8 +1253,8 @@ hpscd_status hpscd_solve_batched_f32(hpscd_ctx* ctx, int32_t count, const hpscd_
     if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
     const Tuned t = batched_choice(ctx, count, sys, opts);
     if (!batched_variant_exists(t.B)) return fail(HPSCD_EINVAL, "batched block %d is not built", t.B);
-    return solve_batched(ctx, count, sys, Xpool, ypool, a0pool, opts, t.B, t.wave_max_m, apool, hist, sweeps_done,
-                         converged, final_rel_resid, info, (hipStream_t)stream);
+    return solve_batched(ctx, count, sys, Xpool, ypool, a0pool, opts, t.B, t.wave_max_m, t.sweeps, apool, hist,
+                         sweeps_done, converged, final_rel_resid, info, (hipStream_t)stream);
   } catch (...) {
     return fail(HPSCD_ENOMEM, "host allocation failure");
   }
@@ -1258,8 +1270,14 @@ hpscd_status hpscd_autotune_batched(hpscd_ctx* ctx, int32_t count, const hpscd_s
     // workgroup shape (four waves of eight chunks per thread, or eight of
     // four), and the work split (systems small enough for one wave share a
     // workgroup, one per wave, or every system gets a whole workgroup).
+    // The first solve records each system's sweep count; every candidate
+    // (and every later solve of this batch) orders its work by it.
+    std::vector<int32_t> sweeps(count, 0);
+    rc = solve_batched(ctx, count, sys, Xpool, ypool, nullptr, opts, 1, batched_rows_per_wave(1), {}, apool,
+                       nullptr, sweeps.data(), nullptr, nullptr, nullptr, (hipStream_t)stream);
+    if (rc != HPSCD_OK) return rc;
     double best = 1e300;
-    Tuned choice{1, batched_rows_per_wave(1)};
+    Tuned choice{1, batched_rows_per_wave(1), sweeps};
     for (int code : {1, 2, 4, 1 + kBatchWide, 2 + kBatchWide, 4 + kBatchWide}) {
       if (!batched_variant_exists(code)) continue;
       const int B = code;  // (the variant code travels as the block argument)
@@ -1267,12 +1285,12 @@ hpscd_status hpscd_autotune_batched(hpscd_ctx* ctx, int32_t count, const hpscd_s
         double t = 1e300;
         for (int rep = 0; rep < 2; ++rep) {
           hpscd_info inf;
-          rc = solve_batched(ctx, count, sys, Xpool, ypool, nullptr, opts, B, split, apool, nullptr, nullptr,
-                             nullptr, nullptr, &inf, (hipStream_t)stream);
+          rc = solve_batched(ctx, count, sys, Xpool, ypool, nullptr, opts, B, split, sweeps, apool, nullptr,
+                             nullptr, nullptr, nullptr, &inf, (hipStream_t)stream);
           if (rc != HPSCD_OK) return rc;
           t = std::min(t, inf.total_ms);
         }
-        if (t < best) { best = t; choice = Tuned{B, split}; }
+        if (t < best) { best = t; choice.B = B; choice.wave_max_m = split; }
       }
     }
     ctx->tuned[batch_key(count, sys)] = choice;
@@ -1334,7 +1352,8 @@ hpscd_status hpscd_batched_plan_create(hpscd_ctx* ctx, int32_t count, const hpsc
       hpscd_batched_plan_destroy(p);
       return fail(HPSCD_EDEVICE, "stream creation failed");
     }
-    rc = prepare_batch(ctx, p->w, count, sys, a0pool != nullptr, opts, t.B, t.wave_max_m, p->bp, p->L, p->cap);
+    rc = prepare_batch(ctx, p->w, count, sys, a0pool != nullptr, opts, t.B, t.wave_max_m, t.sweeps, p->bp, p->L,
+                       p->cap);
     if (rc != HPSCD_OK) { hpscd_batched_plan_destroy(p); return rc; }
     p->grid = batched_grid(ctx, p->bp, t.B);
     if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
