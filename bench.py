@@ -137,6 +137,20 @@ def measured_traffic(key: str, sweeps: float):
     return rec["hbm_bytes_per_sweep"] * sweeps
 
 
+def measured_launch_traffic(key: str):
+    """HBM bytes per launch of a kernel from the committed counter runs, or
+    None when the kernel source changed since."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[key]
+        src = open(os.path.join(ROOT, "paper_2104_12570_amd", "csrc", "hpscd_sweep.hip"), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def _line(metric, value, unit, steps, warmup, ms, higher, dtype, config, **extra):
     out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
            "ms_per_step": ms, "higher_is_better": higher, "scaling": "weak", "vs_baseline": None,
@@ -172,6 +186,18 @@ def _timed(fn, steps, warmup):
         rs.append(fn())
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3 / steps, rs
+
+
+def _calibrate_copy():
+    """One device-to-device copy of 1 GiB (reads 1 GiB, writes 1 GiB): the
+    reference dispatch that scales the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def _stats(v):
@@ -250,6 +276,8 @@ def bench_batched(args):
     log(f"generated batch of {b.count} in {time.perf_counter() - t0:.1f}s")
     Xp = torch.from_numpy(b.Xpool).cuda()
     yp = torch.from_numpy(b.ypool).cuda()
+    if args.calibrate_copy:
+        _calibrate_copy()
     kw = dict(max_sweeps=100, stop=hpscd.STOP_REL_CHANGE, tol=1e-6)
     hpscd.autotune_batched(Xp, yp, b.table, **kw)
     # device time of the kernels from one eager call (HIP events)
@@ -270,17 +298,18 @@ def bench_batched(args):
     sweep_ms = eager.info["sweep_ms"]
     achieved = alg / (sweep_ms / 1e3) / 1e9
     # one call per system (same stop rule), timed once after one warm pass
-    views = [(Xp[b.table[i, 2]: b.table[i, 2] + n[i] * b.table[i, 3]].view(int(n[i]), int(b.table[i, 3])),
-              yp[b.table[i, 4]: b.table[i, 4] + m[i]]) for i in range(b.count)]
-    for Xi, yi in views[:64]:
-        hpscd.solve(Xi, yi, want_hist=False, **kw)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    single_updates = 0
-    for Xi, yi in views:
-        single_updates += hpscd.solve(Xi, yi, want_hist=False, **kw).info["sweeps_done"] * Xi.shape[0]
-    torch.cuda.synchronize()
-    single_ms = (time.perf_counter() - t0) * 1e3
+    single_ms, single_updates = float("nan"), 0
+    if not args.no_per_system:
+        views = [(Xp[b.table[i, 2]: b.table[i, 2] + n[i] * b.table[i, 3]].view(int(n[i]), int(b.table[i, 3])),
+                  yp[b.table[i, 4]: b.table[i, 4] + m[i]]) for i in range(b.count)]
+        for Xi, yi in views[:64]:
+            hpscd.solve(Xi, yi, want_hist=False, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for Xi, yi in views:
+            single_updates += hpscd.solve(Xi, yi, want_hist=False, **kw).info["sweeps_done"] * Xi.shape[0]
+        torch.cuda.synchronize()
+        single_ms = (time.perf_counter() - t0) * 1e3
     log("batched:", eager.info)
     return _line("coord_updates_per_s", updates / (ms / 1e3), "coord_updates/s", args.steps, args.warmup, ms, True,
                  "f32",
@@ -292,7 +321,8 @@ def bench_batched(args):
                       "ms": single_ms, "coord_updates_per_s": single_updates / (single_ms / 1e3)},
                   "speedup_vs_per_system_calls": single_ms / ms},
                  roofline={"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batched",
+                           "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": measured_launch_traffic("k_batched_4096_systems"), "kernel": "k_batched",
                            "alg_bytes_per_launch": alg, "launch_ms": sweep_ms})
 
 
@@ -487,6 +517,8 @@ def main():
     ap.add_argument("--fixed-sweeps", type=int, default=0, help="run exactly this many sweeps (no stop test)")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-system", action="store_true",
+                    help="batched: skip the one-call-per-system comparison (counter runs)")
     ap.add_argument("--ws-train", type=int, default=50_000, help="warmstart: training systems")
     ap.add_argument("--ws-epochs", type=int, default=400, help="warmstart: training epochs")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -508,12 +540,7 @@ def main():
 
     s, Xt, y = _tall(args)
     if args.calibrate_copy:
-        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)  # reads 1 GiB and writes 1 GiB
-        torch.cuda.synchronize()
-        del src, dst
+        _calibrate_copy()
     if args.fixed_sweeps > 0:
         kw = dict(max_sweeps=args.fixed_sweeps, stop=hpscd.STOP_NONE)
     else:
