@@ -696,15 +696,25 @@ __global__ void __launch_bounds__(256) k_resid_batched(const float* Xpool, const
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = 0; i < lim; ++i) acc[i] = (double)ypool[sd.y_off + row + i];
     if (a64pool || a32pool) {
-      for (int64_t j = 0; j < sd.n; ++j) {
-        const double aj = a64pool ? a64pool[sd.a_off + j] : (double)a32pool[sd.a_off + j];
-        float4 x = load_chunk<F32>(X, j * sd.ldx + row);
+      auto coef = [&](int64_t j) { return a64pool ? a64pool[sd.a_off + j] : (double)a32pool[sd.a_off + j]; };
+      auto add = [&](float4 x, double aj) {
         if (lim < 4) x = mask_chunk<F32>(x, lim);
         acc[0] = fma(-(double)x.x, aj, acc[0]);
         acc[1] = fma(-(double)x.y, aj, acc[1]);
         acc[2] = fma(-(double)x.z, aj, acc[2]);
         acc[3] = fma(-(double)x.w, aj, acc[3]);
+      };
+      // (eight columns requested before their products are added, columns
+      // in order)
+      int64_t j = 0;
+      for (; j + 8 <= sd.n; j += 8) {
+        float4 x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = load_chunk<F32>(X, (j + u) * sd.ldx + row);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) add(x[u], coef(j + u));
       }
+      for (; j < sd.n; ++j) add(load_chunk<F32>(X, j * sd.ldx + row), coef(j));
     }
     for (int i = 0; i < lim; ++i) {
       sq = fma(acc[i], acc[i], sq);
