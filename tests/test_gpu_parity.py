@@ -454,3 +454,71 @@ def test_abort_from_another_thread(lib, m, n, kw):
     t.join(120)
     assert not t.is_alive()
     assert "e" in box and box["e"].status == lib.EABORTED, box
+
+
+# ------------------------------------------------ memory past the last column
+
+def _nan_tailed(Xt):
+    """Xt (n, ldx) on the GPU as the first n rows of an (n + 16, ldx) tensor
+    whose 16 rows after it (the memory past column n - 1) are NaN: a kernel
+    that reads a column past n would turn the result non-finite."""
+    import torch
+    n, ldx = Xt.shape
+    big = torch.full((n + 16, ldx), float("nan"), dtype=torch.float32, device="cuda")
+    big[:n] = torch.from_numpy(np.ascontiguousarray(Xt)).cuda()
+    return big[:n]
+
+
+@pytest.mark.parametrize("kind,m,kw", [
+    (9, 1500, dict(depth=9)),
+    (8, 3000, dict(depth=8, block=16, flags=4)),
+    (8, 100_003, dict(depth=8, block=16)),
+    (5, 200_001, dict(depth=5, block=8, flags=2)),
+    (2, 50_001, dict(depth=2, block=8, flags=2)),
+    (3, 50_001, dict(depth=3, block=4, flags=2)),
+    (2, 3000, dict(depth=2, block=4, flags=4)),
+])
+def test_no_read_past_last_column(lib, kind, m, kw):
+    """n = 37 (not a multiple of 4, 8 or 16): the last block's missing columns
+    re-read its last valid column, never the NaN memory that follows X."""
+    rng = np.random.default_rng(kind * 7 + m)
+    s = gen.make_system(rng, m, 37, noise=0.01, pad=np.nan)
+    say("past last column", kind, m)
+    r = lib.solve(_nan_tailed(s.Xt), dev(s.y), max_sweeps=3, **kw)
+    assert r.info["kernel_kind"] == kind
+    ref = oracle.solve(s.Xt, s.y, s.m, max_sweeps=3)
+    check_a(r.a.cpu().numpy(), ref.a, info=r.info)
+    check_hist(r.hist, ref.hist)
+    check_final(r, s, ref.a)
+
+
+def test_bf16_chain_no_read_past_last_column(lib):
+    s = gen.make_system(np.random.default_rng(5), 2000, 45, noise=0.01, pad=np.nan)
+    import torch
+    X32 = dev(s.Xt)
+    xb = lib.convert_bf16(X32)
+    n, ldd = xb.shape
+    bigb = torch.full((n + 16, ldd), float("nan"), dtype=torch.bfloat16, device="cuda")
+    bigb[:n] = xb
+    r = lib.solve_bf16(bigb[:n], X32, dev(s.y), max_sweeps=4, depth=9)
+    ref = oracle.solve_bf16_refresh(s.Xt, s.y, s.m, max_sweeps=4)
+    assert r.info["kernel_kind"] == 9 and r.info["block_used"] == 32
+    check_a(r.a.cpu().numpy(), ref.a, info=r.info)
+
+
+def test_batched_no_read_past_last_column(lib):
+    """The batched kernel on a pool followed by NaN memory, every system with
+    n not a multiple of the block."""
+    import torch
+    b = gen.batch(seed=31, count=24, m_lo=256, m_hi=8192, n_lo=5, n_hi=61, pad=np.nan)
+    pool = torch.full((b.Xpool.size + 4096,), float("nan"), dtype=torch.float32, device="cuda")
+    pool[: b.Xpool.size] = torch.from_numpy(b.Xpool).cuda()
+    say("batched past last column", b.count)
+    for block in (1, 2, 4):
+        r = lib.solve_batched(pool[: b.Xpool.size], dev(b.ypool), b.table, max_sweeps=6, block=block)
+        a = r.a.cpu().numpy()
+        for i in range(b.count):
+            sys_ = b.system(i)
+            ao = b.table[i, 5]
+            ref = oracle.solve(sys_.Xt, sys_.y, sys_.m, max_sweeps=6)
+            check_a(a[ao: ao + sys_.n], ref.a, info=(block, i))
