@@ -1195,7 +1195,7 @@ __device__ inline void team_solve(const BatchArgs& A, int sidx, int ttid, float 
   raw xa[B][R], xb[B][R];
   Coef<B> ca, cb;
 
-  auto load_block = [&](raw (&x)[B][R], Coef<B>& cf, int64_t k) {
+  auto block_rsrc = [&](int64_t k) {
     const int64_t bi = k % nb, j0 = bi * B;
     const int nvalid = (n - j0) < B ? (int)(n - j0) : B;
     const int64_t span = (int64_t)nvalid * sd.ldx * 4;
@@ -1204,20 +1204,30 @@ __device__ inline void team_solve(const BatchArgs& A, int sidx, int ttid, float 
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(base >> 32));
     const uint32_t nrec = (uint32_t)__builtin_amdgcn_readfirstlane(
         (int)(span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span));
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), 0, (int)nrec, 0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), 0, (int)nrec,
+                                             0x00020000);
+  };
+  auto load_chunk_at = [&](const __amdgpu_buffer_rsrc_t& rs, int l, int c) {
+    return __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
+  };
+  auto load_block = [&](raw (&x)[B][R], Coef<B>& cf, int64_t k) {
+    const __amdgpu_buffer_rsrc_t rs = block_rsrc(k);
 #pragma unroll
     for (int l = 0; l < B; ++l)
 #pragma unroll
-      for (int c = 0; c < R; ++c)
-        x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], (int)(l * col_bytes), 0));
-    cf.load(rdn, gram, bi, lane);
+      for (int c = 0; c < R; ++c) x[l][c] = load_chunk_at(rs, l, c);
+    cf.load(rdn, gram, k % nb, lane);
   };
 
   auto step = [&](raw (&cur)[B][R], raw (&nxt)[B][R], Coef<B>& ccur, Coef<B>& cnxt, int64_t k) -> bool {
     const int64_t bi = k % nb, j0 = bi * B;
     const int sdone = (int)(k / nb);
-    load_block(nxt, cnxt, k + 1);  // (past the last step: a harmless reread, issued so every path loads alike)
+    // the next block (past the last step: a harmless reread, issued so every
+    // path loads alike): its coefficients now, its columns spread over this
+    // block's dot products, one chunk load between the arithmetic of two
+    // chunks, so the memory pipeline works while the ALUs do
+    cnxt.load(rdn, gram, (k + 1) % nb, lane);
+    const __amdgpu_buffer_rsrc_t rsn = block_rsrc(k + 1);
     float p[NV];
 #pragma unroll
     for (int l = 0; l < B; ++l) {
@@ -1227,6 +1237,8 @@ __device__ inline void team_solve(const BatchArgs& A, int sidx, int ttid, float 
         if (lim[c] < VEC) cur[l][c] = mask_chunk<S>(cur[l][c], lim[c]);
 #pragma unroll
         for (int i = 0; i < VEC; ++i) acc = fmaf(S::get(cur[l][c], i), e[c][i], acc);
+        nxt[l][c] = load_chunk_at(rsn, l, c);
+        __builtin_amdgcn_sched_barrier(0);
       }
       p[l] = acc;
     }
