@@ -109,6 +109,24 @@ def test_batched_equals_single(lib):
         assert rel(a[ao: ao + s.n], one) <= 1e-5
 
 
+def test_batched_tuned_order_changes_no_result(lib):
+    """The autotuner's cost order (sweeps recorded on the live batch) hands
+    out the systems in another order than an untuned call; every system is
+    solved by one team either way, so a, sweeps and the FP64 check are the
+    same bit for bit (same kernel variant: block 4, eight-wave workgroups;
+    every system above one wave's rows, so each is a workgroup team under
+    any work split)."""
+    b = gen.batch(seed=12, count=300, m_lo=1100, m_hi=8192, n_lo=8, n_hi=128)
+    Xp, yp = dev(b.Xpool), dev(b.ypool)
+    kw = dict(max_sweeps=60, stop=lib.STOP_REL_CHANGE, tol=1e-6, block=4, team_threads=512)
+    before = lib.solve_batched(Xp, yp, b.table, **kw)
+    lib.autotune_batched(Xp, yp, b.table, max_sweeps=60, stop=lib.STOP_REL_CHANGE, tol=1e-6)
+    after = lib.solve_batched(Xp, yp, b.table, **kw)
+    assert np.array_equal(before.a.cpu().numpy(), after.a.cpu().numpy())
+    assert np.array_equal(before.sweeps, after.sweeps)
+    assert np.array_equal(before.final_rel_resid, after.final_rel_resid)
+
+
 def test_batched_stop_and_warm_start(lib):
     b = gen.batch(seed=8, count=24, m_lo=256, m_hi=4096, n_lo=8, n_hi=64)
     say("batched stop")

@@ -425,12 +425,13 @@ def test_blocks_in_flight_kernel(lib, kind, team_threads, m, n, stop):
         assert rel(r.a.cpu().numpy(), ref.a) <= 1e-5
 
 
-@pytest.mark.parametrize("m,n,kw", [(1_000_000, 256, {}), (2000, 512, dict(block=16, depth=8))])
+@pytest.mark.parametrize("m,n,kw", [(1_000_000, 256, {}), (2000, 512, dict(block=16, depth=8)),
+                                    (2000, 4096, dict(depth=9))])
 def test_abort_from_another_thread(lib, m, n, kw):
     """hpscd_abort from a second host thread ends a running solve at the next
-    sweep start with EABORTED (the grid kernel, and the wide-block kernel as
-    one workgroup); the solve is bounded (4000 sweeps), so a missed request
-    shows as a failure, not a hang."""
+    sweep start with EABORTED (the grid kernel, the wide-block kernel as one
+    workgroup, the column chain); the solve is bounded (4000 sweeps), so a
+    missed request shows as a failure, not a hang."""
     import threading
     import time
     import torch
