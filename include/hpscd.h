@@ -264,7 +264,11 @@ hpscd_status hpscd_read_stream(hpscd_ctx* ctx, const void* buf, int64_t bytes, i
                                void* stream);
 
 /* Ask a running solve on this context to stop at its next sweep boundary;
- * that solve returns HPSCD_EABORTED.  Safe to call from another thread. */
+ * that solve returns HPSCD_EABORTED.  Safe to call from another thread.  The
+ * request is a store to a word of pinned host memory that the kernels read at
+ * sweep starts: it issues no GPU work, so it takes effect while a persistent
+ * kernel occupies every CU.  A request made while no solve runs is dropped
+ * when the next solve starts. */
 hpscd_status hpscd_abort(hpscd_ctx* ctx);
 
 /* ---------------------------------------------------------------------------

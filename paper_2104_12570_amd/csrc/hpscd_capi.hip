@@ -110,7 +110,8 @@ struct hpscd_ctx {
   BatchWork bw;
   void* host = nullptr;
   size_t host_cap = 0;
-  hipStream_t side = nullptr;
+  int32_t* cancel_h = nullptr;        // cancel word, pinned host memory mapped into the device
+  const int32_t* cancel_d = nullptr;  // its device address
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::map<std::string, Tuned> tuned;
 
@@ -448,6 +449,8 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   double* fnorm2 = reinterpret_cast<double*>(reinterpret_cast<char*>(cb) + offsetof(CtlBlock, fnorm2));
   double* partial = w.partial;
 
+  // a cancel request concerns the solve running when it is made
+  __atomic_store_n(c->cancel_h, 0, __ATOMIC_SEQ_CST);
   HIP_TRY(hipEventRecord(c->ev[0], st));
   HIP_TRY(launch_fill_i32(ctl, sizeof(CtlBlock) / 4, 0, st));
   HIP_TRY(launch_fill_f64(w.hist, hist_len, std::numeric_limits<double>::quiet_NaN(), st));
@@ -500,6 +503,7 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   A.poll_delay = poll_delay_ticks(pl);
   A.thr = o->thr;
   A.order = o->order;
+  A.cancel = c->cancel_d;
   const int64_t total = (int64_t)o->max_sweeps * nb + 1;
   // launch segments: a refresh period, or one sweep when something runs
   // between sweeps (the gradient rule's pass, a column order's statistics)
@@ -707,9 +711,21 @@ hpscd_status hpscd_create(int device, hpscd_ctx** out) {
     }
     for (auto& e : c->ev)
       if (hipEventCreate(&e) != hipSuccess) { delete c; return fail(HPSCD_EDEVICE, "hipEventCreate"); }
-    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
-      delete c;
-      return fail(HPSCD_EDEVICE, "hipStreamCreateWithFlags");
+    {
+      void* hp = nullptr;
+      void* dp = nullptr;
+      if (hipHostMalloc(&hp, 64, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        delete c;
+        return fail(HPSCD_ENOMEM, "pinned cancel word");
+      }
+      c->cancel_h = static_cast<int32_t*>(hp);
+      *c->cancel_h = 0;
+      if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess || !dp) {
+        (void)hipHostFree(hp);
+        delete c;
+        return fail(HPSCD_EDEVICE, "hipHostGetDevicePointer(cancel word)");
+      }
+      c->cancel_d = static_cast<const int32_t*>(dp);
     }
     *out = c;
     g_err.clear();
@@ -729,7 +745,7 @@ void hpscd_destroy(hpscd_ctx* c) {
   c->bw.release();
   if (c->host) (void)hipHostFree(c->host);
   for (auto& e : c->ev) if (e) (void)hipEventDestroy(e);
-  if (c->side) (void)hipStreamDestroy(c->side);
+  if (c->cancel_h) (void)hipHostFree(c->cancel_h);
   delete c;
 }
 
@@ -958,10 +974,7 @@ hpscd_status hpscd_read_stream(hpscd_ctx* ctx, const void* buf, int64_t bytes, i
 
 hpscd_status hpscd_abort(hpscd_ctx* ctx) {
   if (!ctx) return fail(HPSCD_EINVAL, "ctx is NULL");
-  if (!ctx->ctlb.p) return HPSCD_OK;
-  static const int32_t one = 1;
-  HIP_TRY(hipMemcpyAsync(ctx->ctlb.p, &one, 4, hipMemcpyHostToDevice, ctx->side));
-  HIP_TRY(hipStreamSynchronize(ctx->side));
+  __atomic_store_n(ctx->cancel_h, 1, __ATOMIC_SEQ_CST);
   return HPSCD_OK;
 }
 

@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(CT) k_sweep_chain(SolveArgs A) {
         else if (K->stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < K->tol * nrm) st = conv = true;
         else if (K->stop == STOP_REL_RESID && nrm < K->tol * ynorm) st = conv = true;
         if (!st && sdone >= K->max_sweeps) st = true;
-        if (!st && load_flag(&K->ctl[CTL_ABORT]) != 0) stop = 3;
+        if (!st && load_cancel(K->cancel) != 0) stop = 3;
         if (lane == 0) {
           K->hist[sdone] = nrm;
           K->fstat[1] = nrm;

@@ -166,6 +166,14 @@ __device__ inline int32_t load_flag(const int32_t* p) {
   return __hip_atomic_load(const_cast<int32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The cancel word lives in pinned host memory mapped into the device: the
+// host writes it directly, so a request needs no GPU work of its own (a copy
+// could not start while a persistent kernel fills every CU).  The load
+// crosses to host memory (about a microsecond), so kernels issue it early.
+__device__ inline int32_t load_cancel(const int32_t* p) {
+  return __hip_atomic_load(const_cast<int32_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __device__ inline void store_flag(int32_t* p, int32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -175,7 +183,7 @@ __device__ inline uint64_t now_ticks() { return wall_clock64(); }
 
 // Control-word layout shared by the kernels and the host.
 enum Ctl : int {
-  CTL_ABORT = 0,      // host sets non-zero to cancel
+  CTL_ABORT = 0,      // (unused: the cancel word is in host memory, SolveArgs::cancel)
   CTL_ERR = 1,        // kernel-reported error (status code)
   CTL_SWEEPS = 2,     // complete sweeps performed
   CTL_CONVERGED = 3,  // a stop test fired

@@ -35,6 +35,7 @@ struct SolveArgs {
   uint32_t poll_delay;    // ticks between publishing and the first poll of a grid reduction
   int32_t thr;            // Algorithm 2 block width (wide-block kernel, variant 1)
   const int32_t* order;   // [max_sweeps][n] column order (wide-block kernel, variant 2)
+  const int32_t* cancel;  // cancel word in host memory (mapped): non-zero stops the solve at a sweep start
 };
 
 // One system of a batch as the batched kernels see it (element offsets).

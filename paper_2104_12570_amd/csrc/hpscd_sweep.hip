@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(T) k_sweep(SolveArgs A) {
     // Cancellation: workgroup 0 turns its norm partial into NaN at a sweep
     // boundary, which every workgroup then sees in the reduced norm.
     bool aborting = false;
-    if (bi == 0 && wg == 0 && tid == 0 && load_flag(&A.ctl[CTL_ABORT]) != 0) {
+    if (bi == 0 && wg == 0 && tid == 0 && load_cancel(A.cancel) != 0) {
       p[B] = __int_as_float(0x7fc00000);
       aborting = true;
     }
@@ -567,7 +567,7 @@ __global__ void __launch_bounds__(T) k_sweep_px(SolveArgs A) {
       p[B] = acc;
     }
     bool aborting = false;
-    if (bi == 0 && wg == 0 && tid == 0 && load_flag(&A.ctl[CTL_ABORT]) != 0) {
+    if (bi == 0 && wg == 0 && tid == 0 && load_cancel(A.cancel) != 0) {
       p[B] = __int_as_float(0x7fc00000);
       aborting = true;
     }
@@ -766,16 +766,19 @@ __device__ inline KArgs cold_args() {
 }
 
 // --------------------------------------------------------------------------
-// Grid kernel with wide blocks and no prefetch.
+// Grid kernel with wide blocks.
 //
 // One grid-wide reduction per block of B = 16 columns instead of 8: every
 // wave loads its rows of the block, computes the partial sums, and the
 // workgroup then exchanges them with the grid while no column load is in
-// flight, so the exchange's loads and stores never queue behind column data.
-// The block is requested again only after its axpy.  On the 1M x 256 system
-// the column stream of a 16-column block (256 KB per CU) plus one exchange
-// takes less than two exchanges of 8-column blocks, each overlapped with the
-// next block's loads in the same CU memory pipeline.
+// flight, so the exchange's loads and stores never queue behind column data
+// (nor behind other CUs' column bursts in the memory fabric).  The next
+// block's first PF columns are requested as soon as the exchange has
+// completed, into registers of their own, and stream while the totals, the
+// step and the axpy run; its other columns are requested after the axpy.
+// On the 1M x 256 system the column stream of a 16-column block (256 KB per
+// CU) plus one exchange takes less than two exchanges of 8-column blocks,
+// each overlapped with the next block's loads in the same CU memory pipeline.
 // The exchange is spread over the waves: value v of the block is polled and
 // summed by wave v mod NW.  The block's B steps come from its step matrix
 // M = (D + L)^{-1} (precomputed, FP64): da = M g with g the grid-summed dots,
@@ -809,6 +812,9 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
   constexpr int VPW = (NV + NW - 1) / NW;      // values summed by one wave, at most
   constexpr long long TIMED_OUT = 0x7ff8000000000001ll;  // a NaN no arithmetic here produces
   static_assert(B == 16, "the scattered wave sums and the step matrix rows are laid out for 16 columns");
+  // next-block columns requested after the exchange (Algorithm 1 form; the
+  // 1024-thread shape has no registers to spare)
+  constexpr int PF = (V == 0 && T <= 512) ? 2 : 0;
   __shared__ float red[NW][NV];
   __shared__ double stot[NV];
 
@@ -877,11 +883,41 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
     }
   };
 
+  // the first PF columns of block b into xn (the same unconditional,
+  // range-checked loads as the block's other columns)
+  raw xn[PF > 0 ? PF : 1][R];
+  auto prefetch = [&](int b) {
+    b = __builtin_amdgcn_readfirstlane(b);
+    const int jb = b * B;
+    const int nv = (n - jb) < B ? (int)(n - jb) : B;
+    char* base = const_cast<char*>(reinterpret_cast<const char*>(A.X)) + (int64_t)jb * col_bytes;
+    const int64_t span = (int64_t)(nv - 1) * col_bytes + A.ldx * (int64_t)(16 / VEC);
+    const uint32_t nrec = span > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)span;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)nrec, 0x00020000);
+#pragma unroll
+    for (int l = 0; l < (PF > 0 ? PF : 1); ++l) {
+      const int lc = l < nv ? l : nv - 1;
+      const int coff = (int)((int64_t)lc * col_bytes);
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+        xn[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], coff, 0));
+    }
+  };
+  if constexpr (PF > 0) {
+    if (nblocks > 0) prefetch(bi);
+  }
+
   for (int64_t k = 0; k < nblocks; ++k) {
     // (uniform; said explicitly so the column resource stays in scalar
     // registers instead of a per-load loop over distinct values)
     bi = __builtin_amdgcn_readfirstlane(bi);
     const int j0 = bi * B;
+    const int nbi = (bi + 1 == nb) ? 0 : bi + 1;  // (the block after the launch's last: requested, never used)
+    // a cancel request is looked at by one lane of workgroup 0 at a sweep's
+    // first block, read here so that its trip to host memory overlaps the
+    // column stream
+    int32_t cancel_req = 0;
+    if (bi == 0 && wg == 0 && tid == B) cancel_req = load_cancel(cold_args()->cancel);
     // row (lane mod B) of the block's step matrix M: da = M g
     double mr[B];
     {
@@ -916,7 +952,7 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
       }
       const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)nrec, 0x00020000);
 #pragma unroll
-      for (int l = 0; l < B; ++l) {
+      for (int l = PF; l < B; ++l) {
         const int lc = l < nvalid ? l : nvalid - 1;
         int coff;
         if constexpr (ORD) coff = __builtin_amdgcn_readfirstlane((int)((int64_t)ordr[j0 + lc] * col_bytes));
@@ -925,6 +961,15 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
         for (int c = 0; c < R; ++c)
           x[l][c] = __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)boff[c], coff, 0));
       }
+    }
+    if constexpr (PF > 0) {
+      // (after the other columns are requested, so their loads are not held
+      // back by a wait for these)
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int l = 0; l < PF; ++l)
+#pragma unroll
+        for (int c = 0; c < R; ++c) x[l][c] = xn[l][c];
     }
 #pragma unroll
     for (int c = 0; c < R; ++c)
@@ -969,13 +1014,14 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
     lds_barrier();
     bool aborting = false;
     if (A.P == 1) {
+      if constexpr (PF > 0) prefetch(nbi);
       // one workgroup (a system of at most T*R*VEC rows): its sums are the
       // totals, no exchange; a cancel request rides the norm as a NaN
       if (tid < NV) {
         double acc = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) acc += (double)red[w][tid];
-        if (tid == B && bi == 0 && load_flag(&cold_args()->ctl[CTL_ABORT]) != 0)
+        if (tid == B && bi == 0 && cancel_req != 0)
           acc = __longlong_as_double(0x7ff8000000000000ll);
         stot[tid] = acc;
       }
@@ -989,7 +1035,7 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
   #pragma unroll
         for (int w = 0; w < NW; ++w) sacc += red[w][lane];
         // a cancel request rides the norm of a sweep's first block as a NaN
-        if (lane == B && bi == 0 && wg == 0 && load_flag(&cold_args()->ctl[CTL_ABORT]) != 0) {
+        if (lane == B && bi == 0 && wg == 0 && cancel_req != 0) {
           sacc = __int_as_float(0x7fc00000);
           injected = true;
         }
@@ -1013,33 +1059,46 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
           w[q][c] = live ? peek(slot_base + (int64_t)vv * A.P + idx) : ((uint64_t)seq << 32);
         }
       }
-      uint64_t tstart = 0;
-      bool timed_out = false;
-      for (int spin = 0;; ++spin) {
+      // a wave-uniform spin: every exit follows a completed check of the
+      // words, so nothing of the poll is still in flight after the loop
+      auto all_ready = [&]() {
         bool ready = true;
   #pragma unroll
         for (int q = 0; q < VPW; ++q)
   #pragma unroll
           for (int c = 0; c < MAXC; ++c) ready = ready && ((uint32_t)(w[q][c] >> 32) == seq);
-        if (ready) break;
-        if (spin == 0) tstart = now_ticks();
-        else if (now_ticks() - tstart > A.timeout_ticks) {
-          timed_out = true;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-  #pragma unroll
-        for (int q = 0; q < VPW; ++q) {
-          const int v = wave + NW * q;
-          const int vv = v < NV ? v : NV - 1;
-  #pragma unroll
-          for (int c = 0; c < MAXC; ++c) {
-            const int idx = c * WAVE + lane;
-            if ((uint32_t)(w[q][c] >> 32) != seq) w[q][c] = peek(slot_base + (int64_t)vv * A.P + idx);
+        return __ballot(!ready) == 0;
+      };
+      bool timed_out = false;
+      if (!all_ready()) {
+        const uint64_t tstart = now_ticks();
+        do {
+          if (now_ticks() - tstart > A.timeout_ticks) {
+            timed_out = true;
+            break;
           }
-        }
+          __builtin_amdgcn_s_sleep(1);
+  #pragma unroll
+          for (int q = 0; q < VPW; ++q) {
+            const int v = wave + NW * q;
+            const int vv = v < NV ? v : NV - 1;
+  #pragma unroll
+            for (int c = 0; c < MAXC; ++c) {
+              const int idx = c * WAVE + lane;
+              if ((uint32_t)(w[q][c] >> 32) != seq) w[q][c] = peek(slot_base + (int64_t)vv * A.P + idx);
+            }
+          }
+        } while (!all_ready());
       }
       const bool any_timeout = __ballot(timed_out) != 0;
+      if constexpr (PF > 0) {
+        // the exchange is done: the next block's first columns stream while
+        // the totals, the step and the axpy run (requested earlier, during
+        // the exchange, they would slow every other CU's polls)
+        __builtin_amdgcn_sched_barrier(0);
+        prefetch(nbi);
+        __builtin_amdgcn_sched_barrier(0);
+      }
       // fixed order: per lane over its chunks, then across the lanes
   #pragma unroll
       for (int q = 0; q < VPW; ++q) {
@@ -1065,7 +1124,7 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
     const double nrm = sqrt(nrm2);
     if (!(nrm2 <= DBL_MAX)) {
       if (wg == 0 && tid == 0) {
-        const bool ab = aborting || (A.P == 1 && load_flag(&cold_args()->ctl[CTL_ABORT]) != 0);
+        const bool ab = aborting || (A.P == 1 && load_cancel(cold_args()->cancel) != 0);
         store_flag(&cold_args()->ctl[CTL_ERR], ab ? ERR_ABORTED : ERR_NONFINITE);
       }
       finalize(sdone, false, (int64_t)sdone * n + j0, nrm2);
@@ -1125,10 +1184,12 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
         (void)__hip_atomic_fetch_add(&A.a64[j], dl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
-    bi = (bi + 1 == nb) ? 0 : bi + 1;
+    bi = nbi;
     if (bi == 0) ++sdone;
     ++seq;
   }
+  // no prefetched column may still be in flight when the workgroup ends
+  if constexpr (PF > 0) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 #pragma unroll
   for (int c = 0; c < R; ++c) {
     const int64_t r0 = wg_row0 + (int64_t)VEC * (tid + T * c);
@@ -1379,7 +1440,7 @@ struct Variant {
   X_(F32, 512, 2, 8, 2) X_(F32, 512, 2, 4, 1) X_(F32, 256, 4, 4, 1) X_(F32, 256, 4, 8, 2) X_(BF16, 512, 1, 8, 2)
 #define HPSCD_XENTRY(S, T, R, B, NPW) \
   {T, R, B, HPSCD_IS_BF16_##S, true, 5, reinterpret_cast<const void*>(&k_sweep_px<S, T, R, B, NPW>), T, 0},
-// kind 8: wide blocks, no prefetch
+// kind 8: wide blocks (the next block's first columns requested after each exchange)
 #define HPSCD_WIDE_VARIANTS(X_) X_(F32, 512, 2, 16) X_(BF16, 512, 1, 16) X_(F32, 256, 4, 16) X_(F32, 1024, 1, 16) \
   X_(F32, 512, 1, 16) X_(F32, 256, 1, 16)
 #define HPSCD_WBENTRY(S, T, R, B) \

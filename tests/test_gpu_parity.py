@@ -457,6 +457,14 @@ def test_abort_from_another_thread(lib, m, n, kw):
     assert "e" in box and box["e"].status == lib.EABORTED, box
 
 
+def test_abort_before_solve_is_dropped(lib):
+    """A cancel request made while no solve runs does not end the next one."""
+    s = gen.tall_small(m=3000, n=40)
+    lib.abort()
+    r = lib.solve(dev(s.Xt), dev(s.y), max_sweeps=3)
+    assert r.info["sweeps_done"] == 3
+
+
 # ------------------------------------------------ memory past the last column
 
 def _nan_tailed(Xt):
