@@ -617,7 +617,7 @@ def main():
             "traffic": measured_traffic("k_sweep_f32_tall_1000000x256", sweeps)
             if (s.m, s.n, args.fixed_sweeps) == (1_000_000, 256, 0) else None,
             "kernel": {8: "k_sweep_wide (persistent grid, 16-column blocks, no column loads in flight "
-                          "during the exchange)",
+                          "during the exchange; the next block's first two columns requested after it)",
                        5: "k_sweep_px (persistent grid, polling waves fed through LDS)",
                        2: "k_sweep (persistent grid, 2-block ring)",
                        3: "k_sweep (persistent grid, 3-block ring)"}.get(info["kernel_kind"],

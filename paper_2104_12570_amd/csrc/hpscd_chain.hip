@@ -216,6 +216,10 @@ __global__ void __launch_bounds__(CT) k_sweep_chain(SolveArgs A) {
   auto step = [&](raw(&x)[B], raw(&xfree)[B], double(&mload)[MPT], double(&mnext)[MPT]) -> bool {
     bi = __builtin_amdgcn_readfirstlane(bi);
     const int64_t j0 = (int64_t)bi * B;
+    // a cancel request, looked at by wave 0 at a sweep's first block: read
+    // before the block's work so that its trip to host memory overlaps it
+    int32_t cancel_req = 0;
+    if (bi == 0 && wave == 0) cancel_req = load_cancel(kargs()->cancel);
     load_m(mload, adv(bi, 3));
     const BlockRef ahead = block_ref(adv(bi, 2));
     // partial sums of this thread's rows: the B dots and ||e||^2
@@ -283,7 +287,7 @@ __global__ void __launch_bounds__(CT) k_sweep_chain(SolveArgs A) {
         else if (K->stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < K->tol * nrm) st = conv = true;
         else if (K->stop == STOP_REL_RESID && nrm < K->tol * ynorm) st = conv = true;
         if (!st && sdone >= K->max_sweeps) st = true;
-        if (!st && load_cancel(K->cancel) != 0) stop = 3;
+        if (!st && cancel_req != 0) stop = 3;
         if (lane == 0) {
           K->hist[sdone] = nrm;
           K->fstat[1] = nrm;
