@@ -84,8 +84,8 @@ typedef struct {
                            5: grid kernel whose polling waves never wait behind column loads
                            (their rows arrive through LDS); 8: 16-column blocks through each
                            block's precomputed step matrix, no column loads in flight during the
-                           exchange (a grid, or one workgroup without exchange for at most 4096
-                           rows); 9: the column chain of a short system (at most 2048 rows) on one
+                           exchange, the next block's first two columns requested right after it
+                           (a grid, or one workgroup without exchange for at most 4096 rows); 9: the column chain of a short system (at most 2048 rows) on one
                            workgroup, 16 FP32 or 32 bfloat16 columns per block through its step
                            matrix, the next block's columns and step matrix in flight (the library
                            choice for such systems when the options allow it: block 0 or that
@@ -102,6 +102,11 @@ typedef struct {
                            method, an index outside 0..n-1 is an error the caller must not make).  The
                            statistics of the sweep's 16-column blocks are recomputed before every sweep
                            (one more pass over X per sweep); X must be smaller than 4 GiB. */
+  int32_t spin_timeout_us; /* bound on every wait of a grid's workgroups for one another (each grid
+                              reduction), in microseconds; 0 = 10 s.  A wait past it ends the solve with
+                              HPSCD_ETIMEOUT (a and the history are then invalid).  A bound under
+                              2.4 us also shortens the pause before a reduction's first poll to half
+                              the bound.  Must be >= 0. */
 } hpscd_opts;
 
 typedef struct {

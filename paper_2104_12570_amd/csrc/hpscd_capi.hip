@@ -148,6 +148,7 @@ hpscd_status validate_opts(const hpscd_opts* o) {
   if (o->stop < HPSCD_STOP_NONE || o->stop > HPSCD_STOP_REL_GRAD)
     return fail(HPSCD_EINVAL, "unknown stop rule %d", o->stop);
   if (o->thr < 0) return fail(HPSCD_EINVAL, "thr must be >= 0 (got %d)", o->thr);
+  if (o->spin_timeout_us < 0) return fail(HPSCD_EINVAL, "spin_timeout_us must be >= 0 (got %d)", o->spin_timeout_us);
   if (o->thr > 1 && o->order) return fail(HPSCD_EINVAL, "thr > 1 (Algorithm 2) and a column order are exclusive");
   if ((o->thr > 1 || o->order) && o->depth != 0 && o->depth != 8)
     return fail(HPSCD_EINVAL, "Algorithm 2 and column orders run on the wide-block kernel (depth 8) only");
@@ -499,8 +500,10 @@ hpscd_status solve_single(hpscd_ctx* c, int64_t m, int64_t n, const void* Xs, in
   A.check_cols = (o->stop == HPSCD_STOP_REL_RESID) ? o->check_cols : 0;
   A.P = pl.P;
   A.rows_per_wg = pl.rpw;
-  A.timeout_ticks = kTimeoutTicks;
-  A.poll_delay = poll_delay_ticks(pl);
+  // every spin-wait is bounded: 10 s of the 100 MHz clock, or the caller's
+  // bound (a bound below two first-poll pauses also halves that pause)
+  A.timeout_ticks = o->spin_timeout_us > 0 ? (uint64_t)o->spin_timeout_us * 100 : kTimeoutTicks;
+  A.poll_delay = (uint32_t)std::min<uint64_t>(poll_delay_ticks(pl), A.timeout_ticks / 2);
   A.thr = o->thr;
   A.order = o->order;
   A.cancel = c->cancel_d;

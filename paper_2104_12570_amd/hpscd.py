@@ -53,7 +53,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("max_sweeps", ctypes.c_int32), ("stop", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("check_cols", ctypes.c_int64), ("refresh_cols", ctypes.c_int64), ("block", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("team_threads", ctypes.c_int32), ("depth", ctypes.c_int32),
-                ("thr", ctypes.c_int32), ("order", ctypes.c_void_p)]
+                ("thr", ctypes.c_int32), ("order", ctypes.c_void_p), ("spin_timeout_us", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -140,7 +140,7 @@ def last_error() -> str:
 
 
 def make_opts(max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols=0, refresh_cols=0, block=0, flags=0,
-              team_threads=0, depth=0, thr=0, order_ptr=0) -> Opts:
+              team_threads=0, depth=0, thr=0, order_ptr=0, spin_timeout_us=0) -> Opts:
     o = Opts()
     _lib.hpscd_default_opts(ctypes.byref(o))
     o.max_sweeps, o.stop, o.tol = int(max_sweeps), int(stop), float(tol)
@@ -149,6 +149,7 @@ def make_opts(max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols=0, refresh_col
     o.depth = int(depth)
     o.thr = int(thr)
     o.order = int(order_ptr) or None
+    o.spin_timeout_us = int(spin_timeout_us)
     return o
 
 
@@ -234,7 +235,8 @@ class Result:
 
 
 def solve(Xt, y, a0=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols=0, block=0, flags=0,
-          team_threads=0, depth=0, want_hist=True, thr=0, order=None, refresh_cols=0) -> Result:
+          team_threads=0, depth=0, want_hist=True, thr=0, order=None, refresh_cols=0,
+          spin_timeout_us=0) -> Result:
     """Solve X·a = y (Algorithm 1, single precision) on the GPU.
 
     Xt: (n, ldx) float32 CUDA tensor (column j of X in Xt[j, :m]); y: (m,).
@@ -253,7 +255,7 @@ def solve(Xt, y, a0=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols
             raise ValueError("order must have shape (>= max_sweeps, n)")
     a = torch.empty(n, dtype=torch.float32, device=Xt.device)
     opts = make_opts(max_sweeps, stop, tol, check_cols, refresh_cols, block, flags, team_threads, depth, thr,
-                     order.data_ptr() if order is not None else 0)
+                     order.data_ptr() if order is not None else 0, spin_timeout_us)
     hist = np.full(max_sweeps + 1, np.nan) if want_hist else None
     info = Info()
     _check(_lib.hpscd_solve_f32(context(Xt.device.index), m, n, _ptr(Xt), ldx, _ptr(y), _ptr(a0),

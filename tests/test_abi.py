@@ -41,11 +41,11 @@ def test_struct_layouts_match_header(hp):
 #include <stddef.h>
 #include "hpscd.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hpscd_opts), sizeof(hpscd_info),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(hpscd_opts), sizeof(hpscd_info),
          sizeof(hpscd_sys), offsetof(hpscd_opts, tol), offsetof(hpscd_info, final_norm),
          offsetof(hpscd_info, total_ms), offsetof(hpscd_sys, tol), offsetof(hpscd_info, kernel_kind),
          offsetof(hpscd_opts, thr), offsetof(hpscd_opts, order), offsetof(hpscd_info, diverged),
-         offsetof(hpscd_info, rel_grad));
+         offsetof(hpscd_info, rel_grad), offsetof(hpscd_opts, spin_timeout_us));
   return 0;
 }
 '''
@@ -58,7 +58,7 @@ int main(void) {
     assert got == [ctypes.sizeof(hp.Opts), ctypes.sizeof(hp.Info), ctypes.sizeof(hp.Sys),
                    hp.Opts.tol.offset, hp.Info.final_norm.offset, hp.Info.total_ms.offset, hp.Sys.tol.offset,
                    hp.Info.kernel_kind.offset, hp.Opts.thr.offset, hp.Opts.order.offset, hp.Info.diverged.offset,
-                   hp.Info.rel_grad.offset]
+                   hp.Info.rel_grad.offset, hp.Opts.spin_timeout_us.offset]
 
 
 def test_version(hp):
@@ -199,6 +199,14 @@ def test_wide_block_needs_the_wide_kernel(hp):
     assert hp.validate(100, 10, 4096, 100, 4, 64, hp.make_opts(5, block=16), 128) == hp.OK
     assert hp.validate(100, 10, 4096, 100, 4, 64, hp.make_opts(5, block=16, depth=5), 128) == hp.EINVAL
     assert "depth 8" in hp.last_error()
+
+
+def test_spin_timeout_option(hp):
+    """The bound on grid waits: 0 keeps the default, a negative bound is rejected."""
+    assert hp.validate(100, 10, 4096, 100, 4, 64, hp.make_opts(5, spin_timeout_us=0), 128) == hp.OK
+    assert hp.validate(100, 10, 4096, 100, 4, 64, hp.make_opts(5, spin_timeout_us=50), 128) == hp.OK
+    assert hp.validate(100, 10, 4096, 100, 4, 64, hp.make_opts(5, spin_timeout_us=-1), 128) == hp.EINVAL
+    assert "spin_timeout_us" in hp.last_error()
 
 
 def test_select_rejects_bad_arguments(hp):

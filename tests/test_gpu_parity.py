@@ -457,6 +457,24 @@ def test_abort_from_another_thread(lib, m, n, kw):
     assert "e" in box and box["e"].status == lib.EABORTED, box
 
 
+def test_spin_timeout_ends_the_solve(lib):
+    """A bound of 1 us on the grid waits (the first poll then follows the
+    publish after 0.5 us, before the slowest workgroups have published) ends
+    the solve with ETIMEOUT: every workgroup's wait is bounded, so the kernel
+    exits normally; the next solve on the context runs as if nothing happened."""
+    s = gen.tall_large()
+    X, y = dev(s.Xt), dev(s.y)
+    say("spin timeout")
+    ref = lib.solve(X, y, max_sweeps=3, depth=8)
+    assert ref.info["team_wgs"] > 1
+    with pytest.raises(lib.HPSCDError) as ei:
+        lib.solve(X, y, max_sweeps=3, depth=8, spin_timeout_us=1)
+    assert ei.value.status == lib.ETIMEOUT
+    again = lib.solve(X, y, max_sweeps=3, depth=8)
+    assert np.array_equal(again.a.cpu().numpy(), ref.a.cpu().numpy())
+    assert np.array_equal(again.hist, ref.hist)
+
+
 def test_abort_before_solve_is_dropped(lib):
     """A cancel request made while no solve runs does not end the next one."""
     s = gen.tall_small(m=3000, n=40)
