@@ -32,6 +32,8 @@
 
 #include <float.h>
 
+#include <atomic>
+
 namespace hpscd {
 
 // Coefficients of one block (B reciprocal norms, then the strictly-lower
@@ -1476,12 +1478,23 @@ int sweep_max_workgroups(int T, int R, int B, bool bf16, bool grid, int D, int V
   return v->D >= 5 ? 256 : 512;
 }
 
+// Resident workgroups per CU of a compiled kernel at its launch width: a
+// property of the code object, asked of the runtime once per variant (every
+// planned solve needs it; the query is not free).  0 in a slot = not asked yet.
+static int occupancy_once(std::atomic<int>& slot, const void* fn, int threads) {
+  const int c = slot.load(std::memory_order_relaxed);
+  if (c > 0) return c - 1;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, 0) != hipSuccess) return 0;
+  slot.store(nb + 1, std::memory_order_relaxed);
+  return nb;
+}
+
 int sweep_max_blocks_per_cu(int T, int R, int B, bool bf16, bool grid, int D, int V) {
+  static std::atomic<int> occ[sizeof(kVariants) / sizeof(kVariants[0])];
   const Variant* v = find_variant(T, R, B, bf16, grid, D, V);
   if (!v) return 0;
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn, v->threads, 0) != hipSuccess) return 0;
-  return nb;
+  return occupancy_once(occ[v - kVariants], v->fn, v->threads);
 }
 
 hipError_t launch_sweep(int T, int R, int B, bool bf16, bool grid, int D, const SolveArgs& a, hipStream_t s,
@@ -1519,11 +1532,10 @@ int batched_rows_per_wg(int code) {
   return v ? v->threads * v->R * F32::VEC : 0;
 }
 int batched_max_blocks_per_cu(int code) {
+  static std::atomic<int> occ[sizeof(kBVariants) / sizeof(kBVariants[0])];
   const BVariant* v = find_bvariant(code);
   if (!v) return 0;
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, v->fn, v->threads, 0) != hipSuccess) return 0;
-  return nb;
+  return occupancy_once(occ[v - kBVariants], v->fn, v->threads);
 }
 hipError_t launch_batched(int code, const BatchArgs& a, int grid, hipStream_t s) {
   const BVariant* v = find_bvariant(code);
