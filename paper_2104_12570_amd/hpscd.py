@@ -242,7 +242,9 @@ def solve(Xt, y, a0=None, *, max_sweeps=100, stop=STOP_NONE, tol=0.0, check_cols
     Xt: (n, ldx) float32 CUDA tensor (column j of X in Xt[j, :m]); y: (m,).
     thr > 1: the parallel solver (Algorithm 2) with blocks of thr columns.
     order: None (cyclic) or an int32 CUDA tensor (>= max_sweeps, n) whose
-    row s-1 lists the columns of sweep s."""
+    row s-1 lists the columns of sweep s.  spin_timeout_us: bound on every
+    wait of a grid's workgroups for one another (0 = 10 s); past it the
+    call raises HPSCDError with status ETIMEOUT."""
     torch = _torch()
     _need_cuda(Xt, "Xt", torch.float32)
     _need_cuda(y, "y", torch.float32)
