@@ -114,7 +114,7 @@ def cpu_baseline(s, budget_s: float = 15.0):
         dt = time.perf_counter() - t0
         sweeps = 1
         if dt < budget_s / 4:
-            sweeps = int(max(2, min(10, budget_s // dt)))
+            sweeps = int(max(2, min(200, budget_s // dt)))
             t0 = time.perf_counter()
             oracle.solve(s.Xt, s.y, s.m, max_sweeps=sweeps)
             dt = time.perf_counter() - t0
