@@ -457,20 +457,23 @@ def test_abort_from_another_thread(lib, m, n, kw):
     assert "e" in box and box["e"].status == lib.EABORTED, box
 
 
-def test_spin_timeout_ends_the_solve(lib):
+@pytest.mark.parametrize("kw", [dict(depth=8), dict(depth=5, block=8), dict(depth=2, block=8),
+                                dict(depth=3, block=8)])
+def test_spin_timeout_ends_the_solve(lib, kw):
     """A bound of 1 us on the grid waits (the first poll then follows the
     publish after 0.5 us, before the slowest workgroups have published) ends
-    the solve with ETIMEOUT: every workgroup's wait is bounded, so the kernel
-    exits normally; the next solve on the context runs as if nothing happened."""
+    the solve with ETIMEOUT, on every grid kernel: every workgroup's wait is
+    bounded, so the kernel exits normally; the next solve on the context runs
+    as if nothing happened."""
     s = gen.tall_large()
     X, y = dev(s.Xt), dev(s.y)
-    say("spin timeout")
-    ref = lib.solve(X, y, max_sweeps=3, depth=8)
-    assert ref.info["team_wgs"] > 1
+    say("spin timeout", kw)
+    ref = lib.solve(X, y, max_sweeps=3, **kw)
+    assert ref.info["team_wgs"] > 1 and ref.info["kernel_kind"] == kw["depth"]
     with pytest.raises(lib.HPSCDError) as ei:
-        lib.solve(X, y, max_sweeps=3, depth=8, spin_timeout_us=1)
+        lib.solve(X, y, max_sweeps=3, spin_timeout_us=1, **kw)
     assert ei.value.status == lib.ETIMEOUT
-    again = lib.solve(X, y, max_sweeps=3, depth=8)
+    again = lib.solve(X, y, max_sweeps=3, **kw)
     assert np.array_equal(again.a.cpu().numpy(), ref.a.cpu().numpy())
     assert np.array_equal(again.hist, ref.hist)
 
