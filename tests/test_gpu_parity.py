@@ -457,6 +457,20 @@ def test_abort_from_another_thread(lib, m, n, kw):
     assert "e" in box and box["e"].status == lib.EABORTED, box
 
 
+@pytest.mark.parametrize("n,warm", [(1, False), (2, False), (17, False), (33, True)])
+def test_wide_grid_few_columns(lib, n, warm):
+    """The wide-block grid with fewer columns than one block, one column past
+    a block, and a warm start: the next block's first two columns, requested
+    after each exchange, are the block's own again when a sweep has one
+    block (n <= 16), and the last valid column when the block holds one."""
+    rng = np.random.default_rng(100 + n)
+    s = gen.make_system(rng, 200_000, n, noise=0.01, pad=np.nan)
+    a0 = rng.standard_normal(n).astype(np.float32) if warm else None
+    say("wide grid few columns", n, warm)
+    r, _ = check(lib, s, 6, depth=8, flags=lib.F_FORCE_GRID, **({"a0": a0} if warm else {}))
+    assert r.info["kernel_kind"] == 8 and r.info["team_wgs"] > 1
+
+
 @pytest.mark.parametrize("kw", [dict(depth=8), dict(depth=5, block=8), dict(depth=2, block=8),
                                 dict(depth=3, block=8)])
 def test_spin_timeout_ends_the_solve(lib, kw):
