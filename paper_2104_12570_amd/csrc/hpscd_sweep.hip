@@ -1388,10 +1388,13 @@ __global__ void __launch_bounds__(BShape<W>::T) k_batched(BatchArgs A) {
   __shared__ int s_item;
   const int tid = threadIdx.x, wave = tid / WAVE;
   for (;;) {
+    // the next item is taken only once every wave is done with the last one:
+    // taken as soon as wave 0 was done, it waited, reserved, for the
+    // workgroup's slowest wave while other workgroups ran out of work
+    __syncthreads();
     if (tid == 0) s_item = atomicAdd(A.queue, 1);
     __syncthreads();
     const int it = s_item;
-    __syncthreads();
     if (it >= A.nitems) break;
     const WorkItem w = A.items[it];
     if (w.mode == 0) {
