@@ -287,6 +287,7 @@ __global__ void __launch_bounds__(CT) k_sweep_chain(SolveArgs A) {
         else if (K->stop == STOP_REL_CHANGE && sdone >= 1 && (prev_norm - nrm) < K->tol * nrm) st = conv = true;
         else if (K->stop == STOP_REL_RESID && nrm < K->tol * ynorm) st = conv = true;
         if (!st && sdone >= K->max_sweeps) st = true;
+        asm volatile("" : "+v"(cancel_req));  // (keeps the test, and the wait for the load, here)
         if (!st && cancel_req != 0) stop = 3;
         if (lane == 0) {
           K->hist[sdone] = nrm;

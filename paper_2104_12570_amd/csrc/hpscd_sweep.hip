@@ -920,6 +920,8 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
     // column stream
     int32_t cancel_req = 0;
     if (bi == 0 && wg == 0 && tid == B) cancel_req = load_cancel(cold_args()->cancel);
+    // (its value is hidden from the optimiser until it is used below, so the
+    // test is not hoisted here, where it would wait for the load at once)
     // row (lane mod B) of the block's step matrix M: da = M g
     double mr[B];
     {
@@ -1014,6 +1016,7 @@ __global__ void __launch_bounds__(T) k_sweep_wide(SolveArgs A) {
       if (lane == 0) red[wave][B] = tn;
     }
     lds_barrier();
+    asm volatile("" : "+v"(cancel_req));
     bool aborting = false;
     if (A.P == 1) {
       if constexpr (PF > 0) prefetch(nbi);
